@@ -1,0 +1,458 @@
+// Sweep kernels of the explicit RBF-FD iteration (Sec. II-C, the Jacobi step
+// u <- u + dt (L_h u - f) with L_h u at a node a weighted sum over its support,
+// Sec. II).  All of them read the packed operator (sliced ELL, 64 rows per
+// slice, entries of a slice stored entry-major so that one wavefront reads
+// contiguous 256 B index and 512 B weight lines per support entry).
+//
+// The sweep is bound by HBM bandwidth: per interior node-update it must move
+// 4n bytes of indices, 8n of weights, and 24 of f, u and u_new.  Index and
+// weight streams are read once per sweep and use non-temporal loads so that
+// the gathered solution vector stays in L2 / Infinity Cache.  Rows of a slice
+// are spatial neighbours and support entries are sorted by column id, so the
+// k-th gathers of a wavefront fall on a few adjacent cache lines.
+//
+// Workgroups are dispatched round-robin over the 8 XCDs; with xcd_remap each
+// XCD instead owns a contiguous range of slices, so its private L2 holds one
+// contiguous window of the gathered vector instead of eight.
+#include "rbf_internal.h"
+
+namespace rbf {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
+
+__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblk, int remap) {
+    if (!remap) return bid;
+    const int64_t per = nblk >> 3, rem = nblk & 7;
+    const int64_t x = bid & 7, i = bid >> 3;
+    return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned lo = __shfl_xor((unsigned)(v & 0xffffffffu), off, 64);
+        unsigned hi = __shfl_xor((unsigned)(v >> 32), off, 64);
+        unsigned long long o = ((unsigned long long)hi << 32) | lo;
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Max of |values| over the workgroup into *slot, comparing IEEE bit patterns
+// of non-negative doubles (monotone; a NaN outranks every number).
+template <int WAVES>
+__device__ __forceinline__ void block_max_to_slot(unsigned long long bits, unsigned long long *slot) {
+    __shared__ unsigned long long red[WAVES];
+    bits = wave_max_u64(bits);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[wave] = bits;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = red[0];
+#pragma unroll
+        for (int q = 1; q < WAVES; ++q) m = red[q] > m ? red[q] : m;
+        if (m) atomicMax(slot, m);
+    }
+}
+
+// sum_k w[k] * x[idx[k]] over one row's packed entries (k < len).
+template <typename T, int U>
+__device__ __forceinline__ T ell_row_dot(const int32_t *__restrict__ idx, const T *__restrict__ w,
+                                         const T *__restrict__ x, int64_t base, int len) {
+    T acc = T(0);
+    int k = 0;
+    for (; k + U <= len; k += U) {
+        int32_t j[U];
+        T ww[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            j[q] = ld_stream(idx + base + (int64_t)(k + q) * kSlice);
+            ww[q] = ld_stream(w + base + (int64_t)(k + q) * kSlice);
+        }
+        T xx[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) xx[q] = x[j[q]];
+#pragma unroll
+        for (int q = 0; q < U; ++q) acc = fma(ww[q], xx[q], acc);
+    }
+    for (; k < len; ++k) {
+        const int32_t j = ld_stream(idx + base + (int64_t)k * kSlice);
+        const T ww = ld_stream(w + base + (int64_t)k * kSlice);
+        acc = fma(ww, x[j], acc);
+    }
+    return acc;
+}
+
+// One explicit step on every interior row; optionally max |rho| into slot.
+template <int WAVES, int U, bool REDUCE>
+__global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
+    const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
+    const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ f,
+    const double *__restrict__ u_old, double *__restrict__ u_new, double dt, unsigned long long *res_slot,
+    int remap) {
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
+    const int64_t slice = blk * WAVES + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    unsigned long long bits = 0;
+    if (slice < nslices) {
+        const int64_t base = slice_ptr[slice] + lane;
+        const int len = slice_len[slice];
+        const double acc = ell_row_dot<double, U>(idx, w, u_old, base, len);
+        const int64_t row = slice * kSlice + lane;
+        if (row < N_int) {
+            const double rho = acc - f[row];
+            u_new[row] = u_old[row] + dt * rho;
+            bits = (unsigned long long)__double_as_longlong(fabs(rho));
+        }
+    }
+    if (REDUCE) block_max_to_slot<WAVES>(bits, res_slot);
+}
+
+// FP32 step on the correction: e_new = e + dt (L32 e - r).
+template <int WAVES, int U>
+__global__ __launch_bounds__(WAVES * 64) void k_sweep_f32(
+    const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
+    const float *__restrict__ w, int64_t nslices, int64_t N_int, const float *__restrict__ r,
+    const float *__restrict__ e_old, float *__restrict__ e_new, float dt, int remap) {
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
+    const int64_t slice = blk * WAVES + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (slice >= nslices) return;
+    const int64_t base = slice_ptr[slice] + lane;
+    const int len = slice_len[slice];
+    const float acc = ell_row_dot<float, U>(idx, w, e_old, base, len);
+    const int64_t row = slice * kSlice + lane;
+    if (row < N_int) e_new[row] = e_old[row] + dt * (acc - r[row]);
+}
+
+// Lu (and, with f, max |Lu - f| into slot).
+template <int WAVES, int U>
+__global__ __launch_bounds__(WAVES * 64) void k_apply_f64(
+    const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
+    const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ u,
+    double *__restrict__ Lu, const double *__restrict__ f, unsigned long long *res_slot, int remap) {
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
+    const int64_t slice = blk * WAVES + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    unsigned long long bits = 0;
+    if (slice < nslices) {
+        const int64_t base = slice_ptr[slice] + lane;
+        const int len = slice_len[slice];
+        const double acc = ell_row_dot<double, U>(idx, w, u, base, len);
+        const int64_t row = slice * kSlice + lane;
+        if (row < N_int) {
+            if (Lu) Lu[row] = acc;
+            if (f) bits = (unsigned long long)__double_as_longlong(fabs(acc - f[row]));
+        }
+    }
+    if (res_slot) block_max_to_slot<WAVES>(bits, res_slot);
+}
+
+// Outer residual of the refinement loop: r32 = (float)(f - L64 u); e0 = 0;
+// max |f - L64 u| into slot (the residual of u) when slot is given.
+template <int WAVES, int U>
+__global__ __launch_bounds__(WAVES * 64) void k_outer_residual(
+    const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
+    const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ f,
+    const double *__restrict__ u, float *__restrict__ r32, float *__restrict__ e0, unsigned long long *res_slot,
+    int remap) {
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
+    const int64_t slice = blk * WAVES + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    unsigned long long bits = 0;
+    if (slice < nslices) {
+        const int64_t base = slice_ptr[slice] + lane;
+        const int len = slice_len[slice];
+        const double acc = ell_row_dot<double, U>(idx, w, u, base, len);
+        const int64_t row = slice * kSlice + lane;
+        if (row < N_int) {
+            const double r = f[row] - acc;
+            r32[row] = (float)r;
+            e0[row] = 0.0f;
+            bits = (unsigned long long)__double_as_longlong(fabs(r));
+        }
+    }
+    if (res_slot) block_max_to_slot<WAVES>(bits, res_slot);
+}
+
+// Transpose scatter: out[c] += w_rc v_r for interior rows r and interior c.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_transpose_scatter(
+    const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
+    const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ v,
+    double *__restrict__ out) {
+    const int64_t slice = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (slice >= nslices) return;
+    const int64_t row = slice * kSlice + lane;
+    if (row >= N_int) return;
+    const double vr = v[row];
+    const int64_t base = slice_ptr[slice] + lane;
+    const int len = slice_len[slice];
+    for (int k = 0; k < len; ++k) {
+        const int32_t c = ld_stream(idx + base + (int64_t)k * kSlice);
+        const double ww = ld_stream(w + base + (int64_t)k * kSlice);
+        if (c < N_int && ww != 0.0) unsafeAtomicAdd(out + c, ww * vr);
+    }
+}
+
+__global__ void k_adjoint_update(int64_t N_int, double dt, double *__restrict__ lam, double *__restrict__ acc,
+                                 double *__restrict__ tmp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N_int) return;
+    const double l = lam[i] + dt * tmp[i];
+    lam[i] = l;
+    acc[i] += l;
+    tmp[i] = 0.0;
+}
+
+__global__ void k_add_correction(int64_t N_int, double *__restrict__ u, const float *__restrict__ e) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N_int) u[i] += (double)e[i];
+}
+
+// max |u - uref| into slot and per-block partial sums of |u - uref|.
+__global__ __launch_bounds__(256) void k_err_norm(int64_t N, const double *__restrict__ u,
+                                                  const double *__restrict__ uref, double *__restrict__ partials,
+                                                  unsigned long long *max_slot) {
+    __shared__ double ssum[4];
+    unsigned long long bits = 0;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const double d = fabs(u[i] - uref[i]);
+        const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+        bits = b > bits ? b : bits;
+        s += d;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) ssum[threadIdx.x >> 6] = s;
+    block_max_to_slot<4>(bits, max_slot);  // contains __syncthreads
+    if (threadIdx.x == 0) partials[blockIdx.x] = (ssum[0] + ssum[1]) + (ssum[2] + ssum[3]);
+}
+
+__global__ void k_sum_partials(const double *__restrict__ p, int n, double *out) {
+    __shared__ double s[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) a += p[i];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+// Packed-operator builder: thread per (internal row, slot).  Entry k of
+// canonical row r goes to the position of its rank among the row's internal
+// column ids; slots past the row's size hold the row itself with weight 0;
+// rows past N_int (tail of the last slice) hold column 0 with weight 0.
+__global__ void k_pack_ell(int64_t N_int, int32_t n_max, int64_t nslices, const int32_t *__restrict__ perm,
+                           const int32_t *__restrict__ iperm, const int32_t *__restrict__ sten,
+                           const int16_t *__restrict__ nrow, const double *__restrict__ w_can,
+                           const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len,
+                           int32_t *__restrict__ idx, double *__restrict__ w, float *__restrict__ w32) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / n_max;
+    const int k = (int)(t - i * n_max);
+    if (i >= nslices * kSlice) return;
+    const int64_t s = i / kSlice;
+    const int lane = (int)(i - s * kSlice);
+    const int len = slice_len[s];
+    if (k >= len) return;
+    const int64_t base = slice_ptr[s] + lane;
+    if (i >= N_int) {
+        idx[base + (int64_t)k * kSlice] = 0;
+        w[base + (int64_t)k * kSlice] = 0.0;
+        if (w32) w32[base + (int64_t)k * kSlice] = 0.0f;
+        return;
+    }
+    const int64_t r = perm[i];
+    const int n = nrow[r];
+    if (k >= n) {
+        idx[base + (int64_t)k * kSlice] = (int32_t)i;
+        w[base + (int64_t)k * kSlice] = 0.0;
+        if (w32) w32[base + (int64_t)k * kSlice] = 0.0f;
+        return;
+    }
+    const int32_t *row = sten + r * (int64_t)n_max;
+    const int32_t key = iperm[row[k]];
+    int rank = 0;
+    for (int q = 0; q < n; ++q) rank += (iperm[row[q]] < key) ? 1 : 0;
+    const double wk = w_can[r * (int64_t)n_max + k];
+    idx[base + (int64_t)rank * kSlice] = key;
+    w[base + (int64_t)rank * kSlice] = wk;
+    if (w32) w32[base + (int64_t)rank * kSlice] = (float)wk;
+}
+
+__global__ void k_gather(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ src,
+                         double *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[perm[i]];
+}
+__global__ void k_scatter(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ src,
+                          double *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[perm[i]] = src[i];
+}
+template <typename T>
+__global__ void k_fill(int64_t n, T v, T *__restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_scale_interior(int64_t N, int64_t N_int, double a, const double *__restrict__ src,
+                                 double *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) dst[i] = i < N_int ? a * src[i] : 0.0;
+}
+
+inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Dispatch over the tuned (waves per block, unroll) pairs.
+template <template <int, int> class F, typename... A>
+hipError_t dispatch_shape(const SweepCfg &c, A &&...a) {
+#define RBF_CASE(WV, UN) \
+    if (c.waves_per_block == WV && c.unroll == UN) return F<WV, UN>::run(a...);
+    RBF_CASE(2, 4) RBF_CASE(2, 8) RBF_CASE(2, 16)
+    RBF_CASE(4, 4) RBF_CASE(4, 8) RBF_CASE(4, 16)
+    RBF_CASE(8, 4) RBF_CASE(8, 8) RBF_CASE(8, 16)
+#undef RBF_CASE
+    return hipErrorInvalidValue;
+}
+
+template <int WV, int UN>
+struct SweepF64 {
+    static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const double *f, const double *uo, double *un,
+                          double dt, unsigned long long *slot, int remap) {
+        const unsigned g = grid1d(e.nslices, WV);
+        if (slot)
+            hipLaunchKernelGGL((k_sweep_f64<WV, UN, true>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr, e.slice_len,
+                               e.idx, e.w, e.nslices, N_int, f, uo, un, dt, slot, remap);
+        else
+            hipLaunchKernelGGL((k_sweep_f64<WV, UN, false>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr,
+                               e.slice_len, e.idx, e.w, e.nslices, N_int, f, uo, un, dt, slot, remap);
+        return hipGetLastError();
+    }
+};
+
+template <int WV, int UN>
+struct SweepF32 {
+    static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const float *r, const float *eo, float *en,
+                          float dt, int remap) {
+        hipLaunchKernelGGL((k_sweep_f32<WV, UN>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s, e.slice_ptr,
+                           e.slice_len, e.idx, e.w32, e.nslices, N_int, r, eo, en, dt, remap);
+        return hipGetLastError();
+    }
+};
+
+template <int WV, int UN>
+struct ApplyF64 {
+    static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const double *u, double *Lu, const double *f,
+                          unsigned long long *slot, int remap) {
+        hipLaunchKernelGGL((k_apply_f64<WV, UN>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s, e.slice_ptr,
+                           e.slice_len, e.idx, e.w, e.nslices, N_int, u, Lu, f, slot, remap);
+        return hipGetLastError();
+    }
+};
+
+template <int WV, int UN>
+struct OuterRes {
+    static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const double *f, const double *u, float *r32,
+                          float *e0, unsigned long long *slot, int remap) {
+        hipLaunchKernelGGL((k_outer_residual<WV, UN>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
+                           e.slice_ptr, e.slice_len, e.idx, e.w, e.nslices, N_int, f, u, r32, e0, slot, remap);
+        return hipGetLastError();
+    }
+};
+
+}  // namespace
+
+hipError_t launch_pack_ell(hipStream_t s, int64_t N_int, int32_t n_max, const int32_t *perm, const int32_t *iperm,
+                           const int32_t *sten, const int16_t *nrow, const double *w_can, const Ell &e) {
+    const int64_t total = e.nslices * kSlice * (int64_t)n_max;
+    hipLaunchKernelGGL(k_pack_ell, dim3(grid1d(total, 256)), dim3(256), 0, s, N_int, n_max, e.nslices, perm, iperm,
+                       sten, nrow, w_can, e.slice_ptr, e.slice_len, e.idx, e.w, e.w32);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
+                            const double *u_old, double *u_new, double dt, unsigned long long *res_slot) {
+    return dispatch_shape<SweepF64>(c, s, e, N_int, f, u_old, u_new, dt, res_slot, c.xcd_remap);
+}
+
+hipError_t launch_sweep_f32(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const float *r,
+                            const float *e_old, float *e_new, float dt) {
+    return dispatch_shape<SweepF32>(c, s, e, N_int, r, e_old, e_new, dt, c.xcd_remap);
+}
+
+hipError_t launch_apply_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *u,
+                            double *Lu, const double *f, unsigned long long *res_slot) {
+    return dispatch_shape<ApplyF64>(c, s, e, N_int, u, Lu, f, res_slot, c.xcd_remap);
+}
+
+hipError_t launch_outer_residual(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
+                                 const double *u, float *r32, float *e0, unsigned long long *res_slot) {
+    return dispatch_shape<OuterRes>(c, s, e, N_int, f, u, r32, e0, res_slot, c.xcd_remap);
+}
+
+hipError_t launch_add_correction(hipStream_t s, int64_t N_int, double *u, const float *e) {
+    hipLaunchKernelGGL(k_add_correction, dim3(grid1d(N_int, 256)), dim3(256), 0, s, N_int, u, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_err_norm(hipStream_t s, int64_t N, const double *u, const double *uref, double *partials, int nblk,
+                           unsigned long long *max_slot) {
+    hipLaunchKernelGGL(k_err_norm, dim3(nblk), dim3(256), 0, s, N, u, uref, partials, max_slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(hipStream_t s, const double *partials, int n, double *out) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_scatter(hipStream_t s, const Ell &e, int64_t N_int, const double *v, double *out) {
+    hipLaunchKernelGGL((k_transpose_scatter<4>), dim3(grid1d(e.nslices, 4)), dim3(256), 0, s, e.slice_ptr,
+                       e.slice_len, e.idx, e.w, e.nslices, N_int, v, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_update(hipStream_t s, int64_t N_int, double dt, double *lam, double *acc, double *tmp) {
+    hipLaunchKernelGGL(k_adjoint_update, dim3(grid1d(N_int, 256)), dim3(256), 0, s, N_int, dt, lam, acc, tmp);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(hipStream_t s, int64_t n, const int32_t *perm, const double *src, double *dst) {
+    hipLaunchKernelGGL(k_gather, dim3(grid1d(n, 256)), dim3(256), 0, s, n, perm, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *perm, const double *src, double *dst) {
+    hipLaunchKernelGGL(k_scatter, dim3(grid1d(n, 256)), dim3(256), 0, s, n, perm, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(hipStream_t s, int64_t n, double v, double *p) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<double>, dim3(grid1d(n, 256)), dim3(256), 0, s, n, v, p);
+    return hipGetLastError();
+}
+hipError_t launch_fill_f32(hipStream_t s, int64_t n, float v, float *p) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<float>, dim3(grid1d(n, 256)), dim3(256), 0, s, n, v, p);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u64(hipStream_t s, int64_t n, unsigned long long v, unsigned long long *p) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(grid1d(n, 256)), dim3(256), 0, s, n, v, p);
+    return hipGetLastError();
+}
+hipError_t launch_scale_interior(hipStream_t s, int64_t N, int64_t N_int, double a, const double *src, double *dst) {
+    hipLaunchKernelGGL(k_scale_interior, dim3(grid1d(N, 256)), dim3(256), 0, s, N, N_int, a, src, dst);
+    return hipGetLastError();
+}
+
+}  // namespace rbf

@@ -1,0 +1,1199 @@
+// Host runtime of the gfx950 RBF-FD library: the C ABI declared in rbf.h.
+// Argument checks, memory management, the internal node numbering, the
+// iteration controller (chunks of explicit steps captured as HIP graphs, one
+// 16-byte device-to-host read per chunk), the checkpointed forward run and the
+// adjoint, and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cinttypes>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <limits>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "rbf_internal.h"
+
+using namespace rbf;
+
+namespace {
+
+rbf_status fail(rbf_handle *h, rbf_status st, const char *fmt, ...) {
+    if (h) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        h->err = buf;
+    }
+    return st;
+}
+
+#define HIPCHK(h, expr)                                                                         \
+    do {                                                                                        \
+        hipError_t _e = (expr);                                                                 \
+        if (_e != hipSuccess) return fail((h), RBF_EHIP, "%s: %s", #expr, hipGetErrorString(_e)); \
+    } while (0)
+
+#define ALLOC(h, ptr, T, n)                                                                    \
+    do {                                                                                       \
+        (ptr) = dalloc_n<T>((h), (size_t)(n));                                                 \
+        if (!(ptr)) return fail((h), RBF_ENOMEM, "allocation of %zu bytes failed", (size_t)(n) * sizeof(T)); \
+    } while (0)
+
+// Switch to the handle's device for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
+double bits_to_double(unsigned long long b) {
+    double d;
+    std::memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+uint64_t double_bits(double d) {
+    uint64_t b;
+    std::memcpy(&b, &d, sizeof b);
+    return b;
+}
+
+int num_monomials(int dim, int m) {
+    int64_t num = 1, den = 1;
+    for (int i = 1; i <= dim; ++i) {
+        num *= (m + i);
+        den *= i;
+    }
+    return (int)(num / den);
+}
+
+void free_ptr(rbf_handle *h, void *&p) {
+    if (p) dfree(h, p);
+    p = nullptr;
+}
+
+template <typename T>
+void free_t(rbf_handle *h, T *&p) {
+    void *q = (void *)p;
+    free_ptr(h, q);
+    p = nullptr;
+}
+
+void drop_graphs(rbf_handle *h) {
+    for (auto &kv : h->graphs) hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+}
+
+void drop_operator(rbf_handle *h) {
+    drop_graphs(h);
+    free_t(h, h->perm);
+    free_t(h, h->iperm);
+    free_t(h, h->ell.slice_ptr);
+    free_t(h, h->ell.slice_len);
+    free_t(h, h->ell.idx);
+    free_t(h, h->ell.w);
+    free_t(h, h->ell.w32);
+    h->ell = Ell{};
+    free_t(h, h->ua);
+    free_t(h, h->ub);
+    free_t(h, h->fint);
+    free_t(h, h->tmp);
+    free_t(h, h->uref);
+    free_t(h, h->part);
+    free_t(h, h->ea);
+    free_t(h, h->eb);
+    free_t(h, h->r32);
+    h->have_w32 = false;
+}
+
+void drop_weights(rbf_handle *h) {
+    drop_operator(h);
+    free_t(h, h->w_can);
+    h->have_w = false;
+}
+
+void drop_stencils(rbf_handle *h) {
+    drop_weights(h);
+    free_t(h, h->sten);
+    free_t(h, h->nrow);
+    h->nrow_h.clear();
+    h->n_max = 0;
+    h->have_sten = false;
+}
+
+rbf_status reset_status(rbf_handle *h) {
+    DevStatus s{0, 0, std::numeric_limits<int64_t>::max()};
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    std::memcpy(h->hslots + 8, &s, sizeof s);
+    HIPCHK(h, hipMemcpyAsync(h->dstatus, h->hslots + 8, sizeof s, hipMemcpyHostToDevice, h->stream));
+    return RBF_OK;
+}
+
+rbf_status read_status(rbf_handle *h, DevStatus *out) {
+    HIPCHK(h, hipMemcpyAsync(out, h->dstatus, sizeof *out, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return RBF_OK;
+}
+
+constexpr int kErrBlocks = 1024;
+
+// ------------------------------------------------------------------ tuning cache
+std::string cache_path() {
+    const char *p = std::getenv("RBF_AUTOTUNE_CACHE");
+    return p ? std::string(p) : std::string();
+}
+
+std::string read_file(const std::string &path) {
+    std::ifstream f(path);
+    if (!f) return std::string();
+    std::stringstream ss;
+    ss << f.rdbuf();
+    return ss.str();
+}
+
+// The cache file is a JSON object of "key": [a, b, c] entries.
+bool cache_lookup(const std::string &key, int *vals, int nv) {
+    const std::string path = cache_path();
+    if (path.empty()) return false;
+    const std::string s = read_file(path);
+    const std::string pat = "\"" + key + "\": [";
+    const size_t at = s.find(pat);
+    if (at == std::string::npos) return false;
+    const char *c = s.c_str() + at + pat.size();
+    for (int i = 0; i < nv; ++i) {
+        char *end = nullptr;
+        vals[i] = (int)std::strtol(c, &end, 10);
+        if (end == c) return false;
+        c = end;
+        while (*c == ',' || *c == ' ') ++c;
+    }
+    return true;
+}
+
+void cache_store(const std::string &key, const int *vals, int nv) {
+    const std::string path = cache_path();
+    if (path.empty()) return;
+    std::string s = read_file(path);
+    std::vector<std::string> lines;
+    {
+        std::stringstream ss(s);
+        std::string line;
+        while (std::getline(ss, line)) {
+            const size_t q = line.find('"');
+            if (q == std::string::npos) continue;
+            if (line.find("\"" + key + "\"") != std::string::npos) continue;
+            std::string l = line;
+            while (!l.empty() && (l.back() == ',' || l.back() == ' ')) l.pop_back();
+            lines.push_back(l);
+        }
+    }
+    std::string entry = "  \"" + key + "\": [";
+    for (int i = 0; i < nv; ++i) entry += (i ? ", " : "") + std::to_string(vals[i]);
+    entry += "]";
+    lines.push_back(entry);
+    std::ofstream f(path + ".tmp");
+    f << "{\n";
+    for (size_t i = 0; i < lines.size(); ++i) f << lines[i] << (i + 1 < lines.size() ? ",\n" : "\n");
+    f << "}\n";
+    f.close();
+    std::rename((path + ".tmp").c_str(), path.c_str());
+}
+
+}  // namespace
+
+// ====================================================================== memory
+namespace rbf {
+
+void *dalloc(rbf_handle *h, size_t bytes) {
+    void *p = nullptr;
+    if (h->custom_alloc) {
+        p = h->alloc.alloc(bytes, h->alloc.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) h->owned.emplace_back(p, bytes);
+    return p;
+}
+
+void dfree(rbf_handle *h, void *p) {
+    if (!p) return;
+    auto it = std::find_if(h->owned.begin(), h->owned.end(), [p](const std::pair<void *, size_t> &e) { return e.first == p; });
+    if (it == h->owned.end()) return;
+    h->owned.erase(it);
+    if (h->custom_alloc) h->alloc.free(p, h->alloc.ctx);
+    else hipFree(p);
+}
+
+}  // namespace rbf
+
+// ====================================================================== handle
+extern "C" {
+
+const char *rbf_version(void) { return "rbf-mi355x 0.1 (gfx950)"; }
+
+const char *rbf_status_string(rbf_status s) {
+    switch (s) {
+        case RBF_OK: return "ok";
+        case RBF_EINVAL: return "invalid argument";
+        case RBF_ENOMEM: return "out of memory";
+        case RBF_ESINGULAR: return "singular local system";
+        case RBF_EDIVERGED: return "iteration diverged";
+        case RBF_ENOTCONVERGED: return "not converged";
+        case RBF_EOVERFLOW: return "neighbour search capacity exceeded";
+        case RBF_EHIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+const char *rbf_last_error(const rbf_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+rbf_status rbf_create(rbf_handle **out, int device, void *hip_stream, const rbf_allocator *alloc) {
+    if (!out) return RBF_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return RBF_EINVAL;
+    if (alloc && (!alloc->alloc || !alloc->free)) return RBF_EINVAL;
+    rbf_handle *h = new rbf_handle();
+    h->device = device;
+    DeviceGuard g(device);
+    h->stream = (hipStream_t)hip_stream;
+    if (alloc) {
+        h->alloc = *alloc;
+        h->custom_alloc = true;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete h;
+        return RBF_EHIP;
+    }
+    std::snprintf(h->arch, sizeof h->arch, "%s", prop.gcnArchName);
+    h->num_cus = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+        hipHostMalloc((void **)&h->hslots, 16 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+        delete h;
+        return RBF_EHIP;
+    }
+    h->dslots = dalloc_n<unsigned long long>(h, 16);
+    h->dstatus = dalloc_n<DevStatus>(h, 1);
+    if (!h->dslots || !h->dstatus) {
+        rbf_destroy(h);
+        return RBF_ENOMEM;
+    }
+    *out = h;
+    return RBF_OK;
+}
+
+rbf_status rbf_destroy(rbf_handle *h) {
+    if (!h) return RBF_EINVAL;
+    {
+        DeviceGuard g(h->device);
+        if (h->stream) hipStreamSynchronize(h->stream);
+        else hipDeviceSynchronize();
+        drop_graphs(h);
+        while (!h->owned.empty()) dfree(h, h->owned.back().first);
+        if (h->cap) hipStreamDestroy(h->cap);
+        if (h->ev0) hipEventDestroy(h->ev0);
+        if (h->ev1) hipEventDestroy(h->ev1);
+        if (h->hslots) hipHostFree(h->hslots);
+    }
+    delete h;
+    return RBF_OK;
+}
+
+rbf_status rbf_set_stream(rbf_handle *h, void *hip_stream) {
+    if (!h) return RBF_EINVAL;
+    h->stream = (hipStream_t)hip_stream;
+    return RBF_OK;
+}
+
+rbf_status rbf_get_sizes(const rbf_handle *h, int *dim, int64_t *N, int64_t *N_interior, int32_t *n_max) {
+    if (!h) return RBF_EINVAL;
+    if (dim) *dim = h->dim;
+    if (N) *N = h->N;
+    if (N_interior) *N_interior = h->N_int;
+    if (n_max) *n_max = h->n_max;
+    return RBF_OK;
+}
+
+// ====================================================================== nodes
+rbf_status rbf_build_nodes(rbf_handle *h, int dim, int64_t side, double jitter_frac, uint64_t seed,
+                           double *xyz_dev, int8_t *type_dev) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (dim < 1 || dim > 3 || side < 2) return fail(h, RBF_EINVAL, "dim must be 1..3 and side >= 2");
+    if (!(jitter_frac >= 0.0 && jitter_frac < 0.5)) return fail(h, RBF_EINVAL, "jitter_frac must be in [0, 0.5)");
+    if (!xyz_dev || !type_dev) return fail(h, RBF_EINVAL, "null output pointer");
+    int64_t N = 1;
+    for (int a = 0; a < dim; ++a) {
+        if (N > (int64_t)INT32_MAX / side) return fail(h, RBF_EINVAL, "side^dim exceeds 2^31-1");
+        N *= side;
+    }
+    DeviceGuard g(h->device);
+    const double pitch = 1.0 / (double)(side - 1);
+    const double t = jitter_frac * pitch;
+    HIPCHK(h, launch_build_nodes(h->stream, dim, side, pitch, t, seed, xyz_dev, type_dev));
+    return RBF_OK;
+}
+
+rbf_status rbf_set_nodes(rbf_handle *h, int dim, int64_t N, const double *xyz_dev, const int8_t *type_dev) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (dim < 1 || dim > 3) return fail(h, RBF_EINVAL, "dim must be 1..3");
+    if (N < 1 || N > INT32_MAX) return fail(h, RBF_EINVAL, "N must be in 1..2^31-1");
+    if (!xyz_dev || !type_dev) return fail(h, RBF_EINVAL, "null node pointer");
+    DeviceGuard g(h->device);
+    drop_stencils(h);
+    free_t(h, h->xyz);
+    free_t(h, h->type);
+    h->dim = 0;
+    h->N = h->N_int = 0;
+    std::vector<int8_t> th((size_t)N);
+    HIPCHK(h, hipMemcpyAsync(th.data(), type_dev, (size_t)N, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    int64_t nint = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        if (th[i] != 0 && th[i] != 1) return fail(h, RBF_EINVAL, "node %" PRId64 " has type %d (must be 0 or 1)", i, (int)th[i]);
+        nint += th[i] == 0;
+    }
+    ALLOC(h, h->xyz, double, (size_t)dim * N);
+    ALLOC(h, h->type, int8_t, N);
+    HIPCHK(h, hipMemcpyAsync(h->xyz, xyz_dev, sizeof(double) * dim * N, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->type, type_dev, (size_t)N, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->dim = dim;
+    h->N = N;
+    h->N_int = nint;
+    h->type_h.swap(th);
+    return RBF_OK;
+}
+
+// ====================================================================== stencils
+rbf_status rbf_build_stencils(rbf_handle *h, int32_t n_uniform, const int16_t *n_per_node_dev) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (h->N == 0) return fail(h, RBF_EINVAL, "no nodes set");
+    const int64_t N = h->N;
+    const int dim = h->dim;
+    DeviceGuard g(h->device);
+    int32_t n_max = 0;
+    if (n_uniform > 0) {
+        if (n_uniform > N || n_uniform > kMaxSupport)
+            return fail(h, RBF_EINVAL, "support size %d must be <= N (%" PRId64 ") and <= %d", n_uniform, N, kMaxSupport);
+        n_max = n_uniform;
+    } else {
+        if (n_uniform != 0 || !n_per_node_dev) return fail(h, RBF_EINVAL, "need n_uniform > 0 or per-node sizes");
+        std::vector<int16_t> nh((size_t)N);
+        HIPCHK(h, hipMemcpyAsync(nh.data(), n_per_node_dev, sizeof(int16_t) * N, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        for (int64_t i = 0; i < N; ++i) {
+            if (nh[i] < 1 || nh[i] > N || nh[i] > kMaxSupport)
+                return fail(h, RBF_EINVAL, "node %" PRId64 ": support size %d out of range", i, (int)nh[i]);
+            n_max = std::max<int32_t>(n_max, nh[i]);
+        }
+    }
+    drop_stencils(h);
+
+    // bounding box
+    const int nb = 512;
+    double *partials = nullptr;
+    ALLOC(h, partials, double, nb * 6);
+    HIPCHK(h, launch_bbox_partials(h->stream, dim, N, h->xyz, partials, nb));
+    std::vector<double> ph(nb * 6);
+    HIPCHK(h, hipMemcpyAsync(ph.data(), partials, sizeof(double) * nb * 6, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    dfree(h, partials);
+    CellGrid cg{};
+    cg.dim = dim;
+    double lo[3], hi[3], vol = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = INFINITY;
+        hi[a] = -INFINITY;
+        for (int b = 0; b < nb; ++b) {
+            lo[a] = std::min(lo[a], ph[b * 6 + 2 * a]);
+            hi[a] = std::max(hi[a], ph[b * 6 + 2 * a + 1]);
+        }
+    }
+    double maxext = 0.0;
+    for (int a = 0; a < dim; ++a) {
+        if (!std::isfinite(lo[a]) || !std::isfinite(hi[a])) return fail(h, RBF_EINVAL, "non-finite coordinates");
+        maxext = std::max(maxext, hi[a] - lo[a]);
+    }
+    if (!(maxext > 0.0)) maxext = 1.0;
+    int active = 0;
+    for (int a = 0; a < dim; ++a)
+        if (hi[a] - lo[a] > 1e-12 * maxext) {
+            vol *= (hi[a] - lo[a]);
+            ++active;
+        }
+    const double cell = active ? std::pow(vol / (double)N, 1.0 / active) : maxext;
+    cg.ncells = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a < dim) {
+            const double ext = hi[a] - lo[a];
+            int nc = ext > 1e-12 * maxext ? (int)std::floor(ext / cell) : 1;
+            nc = std::max(1, std::min(nc, 1 << 20));
+            cg.nc[a] = nc;
+            cg.lo[a] = lo[a];
+            cg.edge[a] = ext > 1e-12 * maxext ? ext / nc : maxext;
+        } else {
+            cg.nc[a] = 1;
+            cg.lo[a] = 0.0;
+            cg.edge[a] = 1.0;
+        }
+        cg.ncells *= cg.nc[a];
+    }
+    if (cg.ncells > INT32_MAX / 2) return fail(h, RBF_EINVAL, "cell grid too large");
+    // n nodes at density N/vol fill a ball of radius (n * ball_coef)^(1/d)
+    const double unit_ball = dim == 1 ? 2.0 : (dim == 2 ? M_PI : 4.0 * M_PI / 3.0);
+    const double ball_coef = (active == dim ? vol : std::pow(maxext, dim)) / ((double)N * unit_ball);
+    const double margin = 1e-12 * maxext;
+
+    int32_t *cell_of = nullptr, *count = nullptr, *start = nullptr, *ids = nullptr, *cursor = nullptr, *scan = nullptr;
+    double *xyz_c = nullptr;
+    const int64_t nscan = (cg.ncells + 1023) / 1024 + 1;
+    ALLOC(h, cell_of, int32_t, N);
+    ALLOC(h, count, int32_t, cg.ncells);
+    ALLOC(h, start, int32_t, cg.ncells + 1);
+    ALLOC(h, ids, int32_t, N);
+    ALLOC(h, cursor, int32_t, cg.ncells);
+    ALLOC(h, scan, int32_t, nscan);
+    ALLOC(h, xyz_c, double, (size_t)dim * N);
+    HIPCHK(h, hipMemsetAsync(count, 0, sizeof(int32_t) * cg.ncells, h->stream));
+    HIPCHK(h, hipMemsetAsync(cursor, 0, sizeof(int32_t) * cg.ncells, h->stream));
+    HIPCHK(h, launch_bin_nodes(h->stream, cg, N, h->xyz, cell_of, count, start, ids, cursor, scan));
+    HIPCHK(h, launch_coords_by_cell(h->stream, dim, N, h->xyz, ids, xyz_c));
+
+    ALLOC(h, h->sten, int32_t, (size_t)N * n_max);
+    ALLOC(h, h->nrow, int16_t, N);
+    rbf_status st = reset_status(h);
+    if (st) return st;
+    HIPCHK(h, launch_knn_query(h->stream, cg, N, h->xyz, xyz_c, cell_of, start, ids, n_uniform, n_per_node_dev,
+                               n_max, ball_coef, margin, h->sten, h->nrow, h->dstatus));
+    DevStatus ds;
+    st = read_status(h, &ds);
+    dfree(h, cell_of);
+    dfree(h, count);
+    dfree(h, start);
+    dfree(h, ids);
+    dfree(h, cursor);
+    dfree(h, scan);
+    dfree(h, xyz_c);
+    if (st) return st;
+    if (ds.code != 0) {
+        drop_stencils(h);
+        return fail(h, ds.code, "neighbour search failed at node %" PRId64 " (%s)", ds.info, rbf_status_string(ds.code));
+    }
+    h->n_max = n_max;
+    h->nrow_h.resize((size_t)N);
+    HIPCHK(h, hipMemcpyAsync(h->nrow_h.data(), h->nrow, sizeof(int16_t) * N, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->have_sten = true;
+    return RBF_OK;
+}
+
+// ====================================================================== packed operator
+// Internal order: interior rows by descending support size then canonical id,
+// then Dirichlet rows by canonical id.
+static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
+    drop_operator(h);
+    const int64_t N = h->N, N_int = h->N_int;
+    std::vector<int32_t> perm((size_t)N), iperm((size_t)N);
+    {
+        std::vector<int64_t> cnt(kMaxSupport + 2, 0);
+        for (int64_t i = 0; i < N; ++i)
+            if (h->type_h[i] == 0) cnt[h->nrow_h[i]]++;
+        std::vector<int64_t> off(kMaxSupport + 2, 0);
+        int64_t acc = 0;
+        for (int n = kMaxSupport; n >= 1; --n) {
+            off[n] = acc;
+            acc += cnt[n];
+        }
+        int64_t bpos = N_int;
+        for (int64_t i = 0; i < N; ++i) {
+            if (h->type_h[i] == 0) perm[off[h->nrow_h[i]]++] = (int32_t)i;
+            else perm[bpos++] = (int32_t)i;
+        }
+        for (int64_t k = 0; k < N; ++k) iperm[perm[k]] = (int32_t)k;
+    }
+    Ell e;
+    e.nslices = (N_int + kSlice - 1) / kSlice;
+    std::vector<int64_t> sptr((size_t)e.nslices + 1);
+    std::vector<int32_t> slen((size_t)e.nslices);
+    int64_t acc = 0;
+    int32_t mx = 0;
+    for (int64_t s = 0; s < e.nslices; ++s) {
+        int32_t len = 0;
+        for (int64_t i = s * kSlice; i < std::min<int64_t>(N_int, (s + 1) * kSlice); ++i)
+            len = std::max<int32_t>(len, h->nrow_h[perm[i]]);
+        slen[s] = len;
+        sptr[s] = acc;
+        acc += (int64_t)len * kSlice;
+        mx = std::max(mx, len);
+    }
+    sptr[e.nslices] = acc;
+    e.elems = acc;
+    e.max_len = mx;
+    ALLOC(h, h->perm, int32_t, N);
+    ALLOC(h, h->iperm, int32_t, N);
+    ALLOC(h, e.slice_ptr, int64_t, e.nslices + 1);
+    ALLOC(h, e.slice_len, int32_t, std::max<int64_t>(1, e.nslices));
+    ALLOC(h, e.idx, int32_t, std::max<int64_t>(1, e.elems));
+    ALLOC(h, e.w, double, std::max<int64_t>(1, e.elems));
+    if (keep_fp32) ALLOC(h, e.w32, float, std::max<int64_t>(1, e.elems));
+    h->ell = e;
+    HIPCHK(h, hipMemcpyAsync(h->perm, perm.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->iperm, iperm.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(e.slice_ptr, sptr.data(), sizeof(int64_t) * (e.nslices + 1), hipMemcpyHostToDevice, h->stream));
+    if (e.nslices)
+        HIPCHK(h, hipMemcpyAsync(e.slice_len, slen.data(), sizeof(int32_t) * e.nslices, hipMemcpyHostToDevice, h->stream));
+    if (e.nslices)
+        HIPCHK(h, launch_pack_ell(h->stream, N_int, h->n_max, h->perm, h->iperm, h->sten, h->nrow, h->w_can, h->ell));
+    ALLOC(h, h->ua, double, N);
+    ALLOC(h, h->ub, double, N);
+    ALLOC(h, h->fint, double, N);
+    ALLOC(h, h->tmp, double, N);
+    ALLOC(h, h->uref, double, N);
+    ALLOC(h, h->part, double, kErrBlocks + 8);
+    ALLOC(h, h->ea, float, N);
+    ALLOC(h, h->eb, float, N);
+    ALLOC(h, h->r32, float, N);
+    HIPCHK(h, launch_fill_f32(h->stream, N, 0.0f, h->ea));
+    HIPCHK(h, launch_fill_f32(h->stream, N, 0.0f, h->eb));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->have_w32 = keep_fp32 != 0;
+    // a tuned shape for this operator, if cached
+    char key[160];
+    std::snprintf(key, sizeof key, "sweep|%s|%" PRId64 "|%" PRId64 "|%d", h->arch, N_int, e.elems, e.max_len);
+    int v[3];
+    if (cache_lookup(key, v, 3)) {
+        h->cfg.waves_per_block = v[0];
+        h->cfg.unroll = v[1];
+        h->cfg.xcd_remap = v[2];
+    }
+    return RBF_OK;
+}
+
+// ====================================================================== weights
+extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, const int8_t *m_per_node_dev,
+                                          int keep_fp32) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (!h->have_sten) return fail(h, RBF_EINVAL, "no stencils set");
+    const int64_t N = h->N;
+    const int dim = h->dim;
+    DeviceGuard g(h->device);
+    std::vector<int8_t> mh((size_t)N, (int8_t)m_uniform);
+    if (m_uniform < 0) {
+        if (!m_per_node_dev) return fail(h, RBF_EINVAL, "need m_uniform >= 0 or per-node orders");
+        HIPCHK(h, hipMemcpyAsync(mh.data(), m_per_node_dev, (size_t)N, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    for (int64_t i = 0; i < N; ++i)
+        if (h->type_h[i] == 0 && (mh[i] < 0 || mh[i] > kMaxOrder))
+            return fail(h, RBF_EINVAL, "node %" PRId64 ": order %d not in 0..%d", i, (int)mh[i], kMaxOrder);
+    drop_weights(h);
+
+    // group interior rows by (n, m); classes by descending system size
+    std::map<std::pair<int, int>, std::vector<int32_t>> cls;
+    for (int64_t i = 0; i < N; ++i)
+        if (h->type_h[i] == 0) cls[{h->nrow_h[i], mh[i]}].push_back((int32_t)i);
+    struct Cls { int S, n, m; std::vector<int32_t> *rows; };
+    std::vector<Cls> order;
+    for (auto &kv : cls) order.push_back({kv.first.first + num_monomials(dim, kv.first.second), kv.first.first, kv.first.second, &kv.second});
+    std::sort(order.begin(), order.end(), [](const Cls &a, const Cls &b) { return a.S > b.S || (a.S == b.S && a.n > b.n); });
+    std::vector<int32_t> rows;
+    std::vector<int8_t> mrows;
+    const size_t isz = weights_item_bytes();
+    std::vector<char> items;
+    int S_small = 0, S_mid = 0, S_large = 0;
+    int64_t nitems = 0, nlarge = 0;
+    for (auto &c : order) {
+        const int kind = c.S <= weights_small_limit() ? 0 : (c.S <= weights_mid_limit() ? 1 : 2);
+        if (kind == 0) S_small = std::max(S_small, c.S);
+        if (kind == 1) S_mid = std::max(S_mid, c.S);
+        if (kind == 2) S_large = std::max(S_large, c.S);
+        const int per = kind == 0 ? 4 : 1;
+        const int64_t first = (int64_t)rows.size();
+        for (int32_t r : *c.rows) {
+            rows.push_back(r);
+            mrows.push_back((int8_t)c.m);
+        }
+        for (int64_t q = 0; q < (int64_t)c.rows->size(); q += per) {
+            items.resize(items.size() + isz);
+            weights_make_item(items.data() + items.size() - isz, kind, (int)std::min<int64_t>(per, c.rows->size() - q), first + q);
+            ++nitems;
+            nlarge += kind == 2;
+        }
+    }
+    ALLOC(h, h->w_can, double, (size_t)N * h->n_max);
+    HIPCHK(h, launch_fill_f64(h->stream, N * (int64_t)h->n_max, 0.0, h->w_can));
+    if (nitems > 0) {
+        int32_t *d_rows = nullptr, *counter = nullptr;
+        int8_t *d_m = nullptr;
+        char *d_items = nullptr;
+        double *scratch = nullptr;
+        ALLOC(h, d_rows, int32_t, rows.size());
+        ALLOC(h, d_m, int8_t, mrows.size());
+        ALLOC(h, d_items, char, items.size());
+        ALLOC(h, counter, int32_t, 4);
+        HIPCHK(h, hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(d_m, mrows.data(), mrows.size(), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(d_items, items.data(), items.size(), hipMemcpyHostToDevice, h->stream));
+        const int64_t slab = S_large > 0 ? (int64_t)S_large * (S_large + 1) + 32 : 0;
+        const int cand[3] = {8, 16, 32};
+        int grid_max = 0;
+        for (int pc : cand) grid_max = std::max(grid_max, weights_grid(S_small, S_mid, S_large, pc));
+        if (grid_max <= 0) return fail(h, RBF_EHIP, "weight solver does not fit on the device");
+        if (S_large > 0) ALLOC(h, scratch, double, (size_t)slab * grid_max);
+        // panel width: cached choice, else time the candidates on a sample
+        int panel = h->weights_panel;
+        if (S_large > 0) {
+            char key[160];
+            std::snprintf(key, sizeof key, "weights|%s|%d|%d", h->arch, dim, S_large);
+            int v[1];
+            if (cache_lookup(key, v, 1)) {
+                panel = v[0];
+            } else if (nlarge >= 4096) {
+                float best = 1e30f;
+                const int64_t sample = std::min<int64_t>(nlarge, 4 * grid_max);
+                for (int pc : cand) {
+                    HIPCHK(h, hipMemsetAsync(counter, 0, sizeof(int32_t), h->stream));
+                    HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+                    HIPCHK(h, launch_weights_items(h->stream, dim, N, h->xyz, h->sten, h->nrow, h->n_max, d_rows, d_m,
+                                                   h->w_can, scratch, slab, pc, h->dstatus, d_items, sample, counter,
+                                                   0, 0, S_large, weights_grid(0, 0, S_large, pc), nullptr));
+                    HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+                    HIPCHK(h, hipEventSynchronize(h->ev1));
+                    float ms = 0.f;
+                    HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+                    if (ms < best) {
+                        best = ms;
+                        panel = pc;
+                    }
+                }
+                v[0] = panel;
+                cache_store(key, v, 1);
+            }
+            h->weights_panel = panel;
+        }
+        rbf_status st = reset_status(h);
+        if (st) return st;
+        HIPCHK(h, hipMemsetAsync(counter, 0, sizeof(int32_t), h->stream));
+        HIPCHK(h, launch_weights_items(h->stream, dim, N, h->xyz, h->sten, h->nrow, h->n_max, d_rows, d_m, h->w_can,
+                                       scratch, slab, panel, h->dstatus, d_items, nitems, counter, S_small, S_mid,
+                                       S_large, weights_grid(S_small, S_mid, S_large, panel), nullptr));
+        DevStatus ds;
+        st = read_status(h, &ds);
+        dfree(h, d_rows);
+        dfree(h, d_m);
+        dfree(h, d_items);
+        dfree(h, counter);
+        if (scratch) dfree(h, scratch);
+        if (st) return st;
+        if (ds.code != 0) {
+            free_t(h, h->w_can);
+            return fail(h, ds.code, "singular local system at node %" PRId64, ds.info);
+        }
+    }
+    h->have_w = true;
+    return finalize_operator(h, keep_fp32);
+}
+
+// ====================================================================== import / export
+extern "C" rbf_status rbf_get_stencils(rbf_handle *h, int32_t *idx_host) {
+    if (!h || !idx_host) return RBF_EINVAL;
+    if (!h->have_sten) return fail(h, RBF_EINVAL, "no stencils set");
+    DeviceGuard g(h->device);
+    HIPCHK(h, hipMemcpyAsync(idx_host, h->sten, sizeof(int32_t) * h->N * h->n_max, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_get_weights(rbf_handle *h, double *w_host) {
+    if (!h || !w_host) return RBF_EINVAL;
+    if (!h->have_w) return fail(h, RBF_EINVAL, "no weights set");
+    DeviceGuard g(h->device);
+    HIPCHK(h, hipMemcpyAsync(w_host, h->w_can, sizeof(double) * h->N * h->n_max, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_set_stencils(rbf_handle *h, const int32_t *idx_host, int32_t n_max) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (h->N == 0) return fail(h, RBF_EINVAL, "no nodes set");
+    if (!idx_host || n_max < 1 || n_max > kMaxSupport) return fail(h, RBF_EINVAL, "bad stencil array or n_max");
+    const int64_t N = h->N;
+    std::vector<int16_t> nr((size_t)N);
+    for (int64_t r = 0; r < N; ++r) {
+        int n = 0;
+        while (n < n_max && idx_host[r * n_max + n] >= 0) ++n;
+        if (n == 0) return fail(h, RBF_EINVAL, "row %" PRId64 " has an empty stencil", r);
+        for (int k = 0; k < n_max; ++k) {
+            const int32_t v = idx_host[r * n_max + k];
+            if (k < n && v >= N) return fail(h, RBF_EINVAL, "row %" PRId64 ": id %d out of range", r, v);
+            if (k >= n && v != -1) return fail(h, RBF_EINVAL, "row %" PRId64 ": padding must be -1", r);
+        }
+        nr[r] = (int16_t)n;
+    }
+    DeviceGuard g(h->device);
+    drop_stencils(h);
+    ALLOC(h, h->sten, int32_t, (size_t)N * n_max);
+    ALLOC(h, h->nrow, int16_t, N);
+    HIPCHK(h, hipMemcpyAsync(h->sten, idx_host, sizeof(int32_t) * N * n_max, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->nrow, nr.data(), sizeof(int16_t) * N, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->n_max = n_max;
+    h->nrow_h.swap(nr);
+    h->have_sten = true;
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_set_weights(rbf_handle *h, const double *w_host, int keep_fp32) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (!h->have_sten) return fail(h, RBF_EINVAL, "no stencils set");
+    if (!w_host) return fail(h, RBF_EINVAL, "null weights");
+    const int64_t N = h->N, nm = h->n_max;
+    std::vector<double> w((size_t)N * nm);
+    for (int64_t r = 0; r < N; ++r)
+        for (int64_t k = 0; k < nm; ++k) {
+            const bool live = h->type_h[r] == 0 && k < h->nrow_h[r];
+            w[r * nm + k] = live ? w_host[r * nm + k] : 0.0;
+        }
+    DeviceGuard g(h->device);
+    drop_weights(h);
+    ALLOC(h, h->w_can, double, (size_t)N * nm);
+    HIPCHK(h, hipMemcpyAsync(h->w_can, w.data(), sizeof(double) * N * nm, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->have_w = true;
+    return finalize_operator(h, keep_fp32);
+}
+
+// ====================================================================== operators
+extern "C" rbf_status rbf_apply(rbf_handle *h, const double *u_dev, double *Lu_dev) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (!h->have_w || !h->ua) return fail(h, RBF_EINVAL, "no operator");
+    if (!u_dev || !Lu_dev) return fail(h, RBF_EINVAL, "null pointer");
+    DeviceGuard g(h->device);
+    const int64_t N = h->N, Ni = h->N_int;
+    HIPCHK(h, launch_gather(h->stream, N, h->perm, u_dev, h->ua));
+    HIPCHK(h, launch_fill_f64(h->stream, N - Ni, 0.0, h->tmp + Ni));
+    if (Ni) HIPCHK(h, launch_apply_f64(h->stream, h->cfg, h->ell, Ni, h->ua, h->tmp, nullptr, nullptr));
+    HIPCHK(h, launch_scatter(h->stream, N, h->perm, h->tmp, Lu_dev));
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_apply_transpose(rbf_handle *h, const double *v_dev, double *out_dev) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (!h->have_w || !h->ua) return fail(h, RBF_EINVAL, "no operator");
+    if (!v_dev || !out_dev) return fail(h, RBF_EINVAL, "null pointer");
+    DeviceGuard g(h->device);
+    const int64_t N = h->N, Ni = h->N_int;
+    HIPCHK(h, launch_gather(h->stream, N, h->perm, v_dev, h->ua));
+    HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->tmp));
+    if (Ni) HIPCHK(h, launch_transpose_scatter(h->stream, h->ell, Ni, h->ua, h->tmp));
+    HIPCHK(h, launch_scatter(h->stream, N, h->perm, h->tmp, out_dev));
+    return RBF_OK;
+}
+
+static rbf_status residual_internal(rbf_handle *h, const double *u_int, double *res) {
+    HIPCHK(h, launch_fill_u64(h->stream, 1, 0ull, h->dslots));
+    if (h->N_int)
+        HIPCHK(h, launch_apply_f64(h->stream, h->cfg, h->ell, h->N_int, u_int, nullptr, h->fint, h->dslots));
+    HIPCHK(h, hipMemcpyAsync(h->hslots, h->dslots, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    *res = bits_to_double(h->hslots[0]);
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_residual(rbf_handle *h, const double *f_dev, const double *u_dev, double *res_host) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (!h->have_w || !h->ua) return fail(h, RBF_EINVAL, "no operator");
+    if (!f_dev || !u_dev || !res_host) return fail(h, RBF_EINVAL, "null pointer");
+    DeviceGuard g(h->device);
+    HIPCHK(h, launch_gather(h->stream, h->N, h->perm, u_dev, h->ua));
+    HIPCHK(h, launch_gather(h->stream, h->N, h->perm, f_dev, h->fint));
+    return residual_internal(h, h->ua, res_host);
+}
+
+// ====================================================================== graphs
+enum GraphKind { kGraphF64 = 0, kGraphMixed = 1, kGraphAdjoint = 2, kGraphF64Quiet = 3 };
+
+// FP64 chunk: reset the residual slot, `steps` sweeps alternating ua/ub
+// (starting from ua when start == 0), the last one reporting max |rho|.
+static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, double dt, int inner,
+                            hipGraphExec_t *out) {
+    const auto key = std::make_tuple(kind, steps, start + 2 * inner, double_bits(dt));
+    auto it = h->graphs.find(key);
+    if (it != h->graphs.end()) {
+        *out = it->second;
+        return RBF_OK;
+    }
+    const int64_t Ni = h->N_int;
+    hipStream_t s = h->cap;
+    HIPCHK(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    if (kind == kGraphF64 || kind == kGraphF64Quiet) {
+        if (kind == kGraphF64) e = launch_fill_u64(s, 1, 0ull, h->dslots);
+        double *a = start ? h->ub : h->ua, *b = start ? h->ua : h->ub;
+        for (int64_t i = 0; i < steps && e == hipSuccess; ++i) {
+            const bool report = kind == kGraphF64 && i == steps - 1;
+            e = launch_sweep_f64(s, h->cfg, h->ell, Ni, h->fint, a, b, dt, report ? h->dslots : nullptr);
+            std::swap(a, b);
+        }
+    } else if (kind == kGraphMixed) {
+        // one outer pass: r = f - L64 u (its max into slot 0), `inner` FP32
+        // sweeps on e from 0, u += e, error against the reference into slot 1
+        e = launch_fill_u64(s, 2, 0ull, h->dslots);
+        if (e == hipSuccess) e = launch_outer_residual(s, h->cfg, h->ell, Ni, h->fint, h->ua, h->r32, h->ea, h->dslots);
+        float *a = h->ea, *b = h->eb;
+        const float dt32 = (float)dt;
+        for (int i = 0; i < inner && e == hipSuccess; ++i) {
+            e = launch_sweep_f32(s, h->cfg, h->ell, Ni, h->r32, a, b, dt32);
+            std::swap(a, b);
+        }
+        if (e == hipSuccess) e = launch_add_correction(s, Ni, h->ua, a);
+        if (e == hipSuccess && steps)  // steps != 0: the reference is set
+            e = launch_err_norm(s, h->N, h->ua, h->uref, h->part, kErrBlocks, h->dslots + 1);
+    } else if (kind == kGraphAdjoint) {
+        // `steps` transposed steps: tmp += L^T lam (scatter), lam += dt tmp,
+        // acc += lam, tmp = 0.  ua = lam, ub = acc.
+        for (int64_t i = 0; i < steps && e == hipSuccess; ++i) {
+            e = launch_transpose_scatter(s, h->ell, Ni, h->ua, h->tmp);
+            if (e == hipSuccess) e = launch_adjoint_update(s, Ni, dt, h->ua, h->ub, h->tmp);
+        }
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return fail(h, RBF_EHIP, "graph capture: %s", hipGetErrorString(e));
+    }
+    if (e2 != hipSuccess) return fail(h, RBF_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(h, RBF_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    if (h->graphs.size() > 64) drop_graphs(h);
+    h->graphs[key] = exec;
+    *out = exec;
+    return RBF_OK;
+}
+
+// ====================================================================== iterate
+extern "C" rbf_status rbf_iterate(rbf_handle *h, const double *f_dev, double *u_dev, const rbf_iter_params *p,
+                                  rbf_iter_report *rep) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (!p || !rep || !f_dev || !u_dev) return fail(h, RBF_EINVAL, "null pointer");
+    if (!h->have_w || !h->ua) return fail(h, RBF_EINVAL, "no operator: compute or set weights first");
+    if (!std::isfinite(p->dt)) return fail(h, RBF_EINVAL, "dt must be finite");
+    if (p->max_steps < 0 || p->chunk < 1) return fail(h, RBF_EINVAL, "max_steps >= 0 and chunk >= 1 required");
+    if (p->mode != RBF_MODE_FP64 && p->mode != RBF_MODE_MIXED) return fail(h, RBF_EINVAL, "unknown mode %d", p->mode);
+    if (p->mode == RBF_MODE_MIXED && (p->inner_steps < 1 || !h->have_w32))
+        return fail(h, RBF_EINVAL, "mixed mode needs inner_steps >= 1 and FP32 weights (keep_fp32)");
+    if (p->stall_chunks < 0) return fail(h, RBF_EINVAL, "stall_chunks must be >= 0");
+    DeviceGuard g(h->device);
+    std::memset(rep, 0, sizeof *rep);
+    rep->diverged_step = -1;
+    const int64_t N = h->N, Ni = h->N_int;
+    const bool use_ref = p->u_ref_dev != nullptr;
+    const bool err_stop = use_ref && p->err_target > 0.0;
+
+    HIPCHK(h, launch_gather(h->stream, N, h->perm, u_dev, h->ua));
+    HIPCHK(h, hipMemcpyAsync(h->ub, h->ua, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, launch_gather(h->stream, N, h->perm, f_dev, h->fint));
+    if (use_ref) HIPCHK(h, launch_gather(h->stream, N, h->perm, p->u_ref_dev, h->uref));
+    // max |f| over interior rows (tmp = 0 as the reference)
+    HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->tmp));
+    HIPCHK(h, launch_fill_u64(h->stream, 2, 0ull, h->dslots));
+    if (Ni) HIPCHK(h, launch_err_norm(h->stream, Ni, h->fint, h->tmp, h->part, kErrBlocks, h->dslots + 1));
+    HIPCHK(h, hipMemcpyAsync(h->hslots + 1, h->dslots + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    rep->fnorm = bits_to_double(h->hslots[1]);
+    double res0 = 0.0;
+    rbf_status st = residual_internal(h, h->ua, &res0);
+    if (st) return st;
+    rep->res0 = res0;
+    rep->res_last = res0;
+
+    auto finish_errors = [&](double *cur) -> rbf_status {
+        if (!use_ref) return RBF_OK;
+        HIPCHK(h, launch_fill_u64(h->stream, 2, 0ull, h->dslots));
+        HIPCHK(h, launch_err_norm(h->stream, N, cur, h->uref, h->part, kErrBlocks, h->dslots + 1));
+        HIPCHK(h, launch_sum_partials(h->stream, h->part, kErrBlocks, (double *)(h->dslots + 2)));
+        HIPCHK(h, hipMemcpyAsync(h->hslots, h->dslots, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        rep->err_inf = bits_to_double(h->hslots[1]);
+        rep->err_mean_abs = bits_to_double(h->hslots[2]) / (double)N;
+        return RBF_OK;
+    };
+
+    if (!std::isfinite(res0)) {
+        rep->diverged = 1;
+        rep->diverged_step = 0;
+        rep->res_final = res0;
+        st = finish_errors(h->ua);
+        if (st) return st;
+        return fail(h, RBF_EDIVERGED, "non-finite initial residual (diverged at step 0)");
+    }
+
+    const bool tol_stop = p->tol_rel > 0.0;
+    const double tol_abs = p->tol_rel * rep->fnorm;
+    double best = INFINITY;
+    int64_t since_best = 0;
+    int64_t steps = 0;
+    int cur = 0;  // 0: iterate in ua, 1: in ub
+    double dev_ms = 0.0, sweep_ms = 0.0;
+    int64_t sweeps_timed = 0;
+    rbf_status status = (tol_stop || err_stop) ? RBF_ENOTCONVERGED : RBF_OK;
+
+    if (p->mode == RBF_MODE_FP64) {
+        while (steps < p->max_steps) {
+            const int64_t s = std::min<int64_t>(p->chunk, p->max_steps - steps);
+            hipGraphExec_t ex;
+            st = get_graph(h, kGraphF64, s, cur, p->dt, 0, &ex);
+            if (st) return st;
+            HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+            HIPCHK(h, hipGraphLaunch(ex, h->stream));
+            HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+            if (s & 1) cur ^= 1;
+            double *u_now = cur ? h->ub : h->ua;
+            int nslot = 1;
+            if (err_stop) {
+                HIPCHK(h, launch_fill_u64(h->stream, 1, 0ull, h->dslots + 1));
+                HIPCHK(h, launch_err_norm(h->stream, N, u_now, h->uref, h->part, kErrBlocks, h->dslots + 1));
+                nslot = 2;
+            }
+            HIPCHK(h, hipMemcpyAsync(h->hslots, h->dslots, nslot * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            float ms = 0.f;
+            HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+            dev_ms += ms;
+            sweep_ms += ms;
+            sweeps_timed += s;
+            steps += s;
+            rep->checks++;
+            const double res = bits_to_double(h->hslots[0]);
+            rep->res_last = res;
+            if (!std::isfinite(res) || res > 1e6 * res0) {
+                rep->diverged = 1;
+                rep->diverged_step = steps;
+                status = RBF_EDIVERGED;
+                break;
+            }
+            if (err_stop && bits_to_double(h->hslots[1]) <= p->err_target) {
+                rep->err_met = 1;
+                rep->converged = 1;
+                status = RBF_OK;
+                break;
+            }
+            if (tol_stop && res <= tol_abs) {
+                rep->converged = 1;
+                status = RBF_OK;
+                break;
+            }
+            if (res < best) {
+                best = res;
+                since_best = 0;
+            } else if (p->stall_chunks > 0 && ++since_best >= p->stall_chunks) {
+                break;
+            }
+        }
+        h->last_sweep_sec = sweeps_timed ? sweep_ms * 1e-3 / (double)sweeps_timed : 0.0;
+        h->last_sweeps = sweeps_timed;
+    } else {
+        // mixed precision: one graph per outer pass (cur stays 0: u lives in ua)
+        const int inner = p->inner_steps;
+        while (steps < p->max_steps) {
+            hipGraphExec_t ex;
+            st = get_graph(h, kGraphMixed, use_ref ? 1 : 0, 0, p->dt, inner, &ex);
+            if (st) return st;
+            HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+            HIPCHK(h, hipGraphLaunch(ex, h->stream));
+            HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+            HIPCHK(h, hipMemcpyAsync(h->hslots, h->dslots, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            float ms = 0.f;
+            HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+            dev_ms += ms;
+            steps += inner;
+            rep->checks++;
+            const double res = bits_to_double(h->hslots[0]);  // residual of u entering the pass
+            rep->res_last = res;
+            if (!std::isfinite(res) || res > 1e6 * res0) {
+                rep->diverged = 1;
+                rep->diverged_step = steps;
+                status = RBF_EDIVERGED;
+                break;
+            }
+            if (err_stop && bits_to_double(h->hslots[1]) <= p->err_target) {
+                rep->err_met = 1;
+                rep->converged = 1;
+                status = RBF_OK;
+                break;
+            }
+            if (tol_stop && res <= tol_abs) {
+                rep->converged = 1;
+                status = RBF_OK;
+                break;
+            }
+            if (res < best) {
+                best = res;
+                since_best = 0;
+            } else if (p->stall_chunks > 0 && ++since_best >= p->stall_chunks) {
+                break;
+            }
+        }
+    }
+    double *u_fin = cur ? h->ub : h->ua;
+    rep->steps = steps;
+    rep->seconds = dev_ms * 1e-3;
+    HIPCHK(h, launch_scatter(h->stream, N, h->perm, u_fin, u_dev));
+    double resf = 0.0;
+    st = residual_internal(h, u_fin, &resf);
+    if (st) return st;
+    rep->res_final = resf;
+    st = finish_errors(u_fin);
+    if (st) return st;
+    if (status == RBF_EDIVERGED)
+        return fail(h, status, "diverged: residual %g at step %" PRId64 " (initial %g)", rep->res_last, rep->diverged_step, res0);
+    if (status == RBF_ENOTCONVERGED)
+        return fail(h, status, "not converged after %" PRId64 " steps (residual %g, target %g)", steps, rep->res_last, tol_abs);
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_last_sweep_time(const rbf_handle *h, double *seconds_per_sweep, int64_t *sweeps) {
+    if (!h) return RBF_EINVAL;
+    if (seconds_per_sweep) *seconds_per_sweep = h->last_sweep_sec;
+    if (sweeps) *sweeps = h->last_sweeps;
+    return RBF_OK;
+}
+
+// ====================================================================== adjoint
+extern "C" rbf_status rbf_forward_ckpt(rbf_handle *h, const double *f_dev, const double *u0_dev, int64_t K,
+                                       int64_t every, double *ckpt_dev, double *uK_dev, double dt) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (!h->have_w || !h->ua) return fail(h, RBF_EINVAL, "no operator");
+    if (!f_dev || !u0_dev || !uK_dev) return fail(h, RBF_EINVAL, "null pointer");
+    if (K < 1 || every < 1 || every > K || K % every) return fail(h, RBF_EINVAL, "need 1 <= every <= K, K %% every == 0");
+    if (!std::isfinite(dt)) return fail(h, RBF_EINVAL, "dt must be finite");
+    DeviceGuard g(h->device);
+    const int64_t N = h->N;
+    HIPCHK(h, launch_gather(h->stream, N, h->perm, u0_dev, h->ua));
+    HIPCHK(h, hipMemcpyAsync(h->ub, h->ua, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, launch_gather(h->stream, N, h->perm, f_dev, h->fint));
+    if (ckpt_dev) HIPCHK(h, launch_scatter(h->stream, N, h->perm, h->ua, ckpt_dev));
+    int cur = 0;
+    for (int64_t seg = 1; seg <= K / every; ++seg) {
+        hipGraphExec_t ex;
+        rbf_status st = get_graph(h, kGraphF64Quiet, every, cur, dt, 0, &ex);
+        if (st) return st;
+        HIPCHK(h, hipGraphLaunch(ex, h->stream));
+        if (every & 1) cur ^= 1;
+        if (ckpt_dev) HIPCHK(h, launch_scatter(h->stream, N, h->perm, cur ? h->ub : h->ua, ckpt_dev + seg * N));
+    }
+    HIPCHK(h, launch_scatter(h->stream, N, h->perm, cur ? h->ub : h->ua, uK_dev));
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_adjoint_f(rbf_handle *h, const double *gK_dev, int64_t K, int64_t every,
+                                    const double *ckpt_dev, double *grad_f_dev, double dt) {
+    (void)ckpt_dev;  // the gradient with respect to f does not depend on the states
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (!h->have_w || !h->ua) return fail(h, RBF_EINVAL, "no operator");
+    if (!gK_dev || !grad_f_dev) return fail(h, RBF_EINVAL, "null pointer");
+    if (K < 1 || every < 1 || every > K || K % every) return fail(h, RBF_EINVAL, "need 1 <= every <= K, K %% every == 0");
+    if (!std::isfinite(dt)) return fail(h, RBF_EINVAL, "dt must be finite");
+    DeviceGuard g(h->device);
+    const int64_t N = h->N, Ni = h->N_int;
+    // lam (ua) = gK on interior rows; acc (ub) = lam; tmp = 0
+    HIPCHK(h, launch_gather(h->stream, N, h->perm, gK_dev, h->ua));
+    HIPCHK(h, launch_fill_f64(h->stream, N - Ni, 0.0, h->ua + Ni));
+    HIPCHK(h, hipMemcpyAsync(h->ub, h->ua, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->tmp));
+    // K-1 transposed steps, segment by segment from the last checkpoint
+    // interval back to the first; the first interval has one step fewer.
+    const int64_t nseg = K / every;
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t steps = seg == 0 ? every - 1 : every;
+        if (steps <= 0) continue;
+        hipGraphExec_t ex;
+        rbf_status st = get_graph(h, kGraphAdjoint, steps, 0, dt, 0, &ex);
+        if (st) return st;
+        HIPCHK(h, hipGraphLaunch(ex, h->stream));
+    }
+    HIPCHK(h, launch_scale_interior(h->stream, N, Ni, -dt, h->ub, h->tmp));
+    HIPCHK(h, launch_scatter(h->stream, N, h->perm, h->tmp, grad_f_dev));
+    // leave tmp zeroed for the next transposed call
+    HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->tmp));
+    return RBF_OK;
+}
+
+// ====================================================================== autotune
+extern "C" rbf_status rbf_autotune(rbf_handle *h) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (!h->have_w || !h->ua || !h->N_int) return fail(h, RBF_EINVAL, "no operator");
+    DeviceGuard g(h->device);
+    drop_graphs(h);
+    const int64_t Ni = h->N_int;
+    HIPCHK(h, launch_fill_f64(h->stream, h->N, 0.0, h->ua));
+    HIPCHK(h, launch_fill_f64(h->stream, h->N, 0.0, h->ub));
+    HIPCHK(h, launch_fill_f64(h->stream, h->N, 0.0, h->fint));
+    const int reps = 20;
+    float best = 1e30f;
+    SweepCfg bestc = h->cfg;
+    for (int wv : {2, 4, 8})
+        for (int un : {4, 8, 16})
+            for (int rm : {0, 1}) {
+                SweepCfg c;
+                c.waves_per_block = wv;
+                c.unroll = un;
+                c.xcd_remap = rm;
+                HIPCHK(h, launch_sweep_f64(h->stream, c, h->ell, Ni, h->fint, h->ua, h->ub, 0.0, nullptr));
+                HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+                for (int r = 0; r < reps; ++r)
+                    HIPCHK(h, launch_sweep_f64(h->stream, c, h->ell, Ni, h->fint, (r & 1) ? h->ub : h->ua,
+                                               (r & 1) ? h->ua : h->ub, 0.0, nullptr));
+                HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+                HIPCHK(h, hipEventSynchronize(h->ev1));
+                float ms = 0.f;
+                HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+                if (ms < best) {
+                    best = ms;
+                    bestc = c;
+                }
+            }
+    h->cfg = bestc;
+    char key[160];
+    std::snprintf(key, sizeof key, "sweep|%s|%" PRId64 "|%" PRId64 "|%d", h->arch, Ni, h->ell.elems, h->ell.max_len);
+    int v[3] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap};
+    cache_store(key, v, 3);
+    return RBF_OK;
+}
+
+}  // extern "C"

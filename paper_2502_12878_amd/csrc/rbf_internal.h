@@ -1,0 +1,178 @@
+// Internal declarations of the gfx950 RBF-FD library: the handle, the packed
+// operator layout, and the host-side launchers of every kernel family.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "rbf.h"
+
+namespace rbf {
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kSlice = 64;       // rows per slice of the packed operator (= one wavefront)
+constexpr int kMaxSupport = 256; // largest support size accepted
+constexpr int kMaxOrder = 6;     // largest augmentation order accepted
+
+// Device-side status word: set by kernels that detect a failure, read by the
+// host at the next synchronisation.  code = rbf_status, info = node id.
+struct DevStatus {
+    int32_t code;
+    int32_t pad;
+    int64_t info;
+};
+
+// Launch shape of the sweep kernels (chosen by the autotuner).
+struct SweepCfg {
+    int waves_per_block = 4;  // slices (64 rows each) per workgroup
+    int unroll = 8;           // support entries loaded ahead per lane
+    int xcd_remap = 1;        // give each XCD a contiguous range of slices
+    bool operator<(const SweepCfg &o) const {
+        return std::tie(waves_per_block, unroll, xcd_remap) < std::tie(o.waves_per_block, o.unroll, o.xcd_remap);
+    }
+};
+
+// Packed operator: interior rows renumbered first (grouped by support size,
+// then canonical id), Dirichlet rows last.  Slice s covers internal rows
+// [64 s, 64 s + 64); its entries live at slice_ptr[s] + k*64 + lane for
+// k < slice_len[s].  Within a row, entries are sorted by internal column id
+// so that the k-th gathers of neighbouring rows hit neighbouring addresses.
+struct Ell {
+    int64_t nslices = 0;
+    int64_t elems = 0;
+    int32_t max_len = 0;
+    int64_t *slice_ptr = nullptr;  // [nslices + 1]
+    int32_t *slice_len = nullptr;  // [nslices]
+    int32_t *idx = nullptr;        // [elems] internal ids
+    double *w = nullptr;           // [elems]
+    float *w32 = nullptr;          // [elems] or null
+};
+
+}  // namespace rbf
+
+struct rbf_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;   // borrowed
+    hipStream_t cap = nullptr;      // own stream used only for graph capture
+    rbf_allocator alloc{};
+    bool custom_alloc = false;
+    std::vector<std::pair<void *, size_t>> owned;  // live allocations
+    std::string err;
+    char arch[64] = {0};
+    int num_cus = 0;
+
+    // small device/host scratch
+    unsigned long long *dslots = nullptr;  // [16] device
+    unsigned long long *hslots = nullptr;  // [16] pinned host
+    rbf::DevStatus *dstatus = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    // nodes (canonical order)
+    int dim = 0;
+    int64_t N = 0, N_int = 0;
+    double *xyz = nullptr;   // [dim][N]
+    int8_t *type = nullptr;  // [N]
+
+    // stencils and weights (canonical order, row-major [N][n_max])
+    int32_t n_max = 0;
+    int32_t *sten = nullptr;
+    int16_t *nrow = nullptr;  // [N]
+    double *w_can = nullptr;
+    bool have_sten = false, have_w = false, have_w32 = false;
+
+    // internal numbering and packed operator
+    int32_t *perm = nullptr;   // internal -> canonical
+    int32_t *iperm = nullptr;  // canonical -> internal
+    rbf::Ell ell;
+
+    // iteration vectors (internal order)
+    double *ua = nullptr, *ub = nullptr, *fint = nullptr, *tmp = nullptr, *uref = nullptr;
+    double *part = nullptr;   // per-block partial sums
+    float *ea = nullptr, *eb = nullptr, *r32 = nullptr;
+
+    rbf::SweepCfg cfg;
+    int weights_panel = 32;
+    double last_sweep_sec = 0.0;
+    int64_t last_sweeps = 0;
+
+    // cached graphs: key = (kind, steps, start buffer, dt bits) -> executable
+    std::map<std::tuple<int, int64_t, int, uint64_t>, hipGraphExec_t> graphs;
+
+    // host copies used for validation and layout
+    std::vector<int8_t> type_h;
+    std::vector<int16_t> nrow_h;
+};
+
+namespace rbf {
+
+// ---------------------------------------------------------------- memory
+void *dalloc(rbf_handle *h, size_t bytes);
+void dfree(rbf_handle *h, void *p);
+template <typename T>
+T *dalloc_n(rbf_handle *h, size_t n) { return static_cast<T *>(dalloc(h, n * sizeof(T) + 256)); }
+
+// ---------------------------------------------------------------- nodes
+hipError_t launch_build_nodes(hipStream_t s, int dim, int64_t side, double h, double t, uint64_t seed,
+                              double *xyz, int8_t *type);
+
+// ---------------------------------------------------------------- neighbours
+struct CellGrid {
+    int dim;
+    int nc[3];
+    double lo[3];
+    double edge[3];
+    int64_t ncells;
+};
+hipError_t launch_bbox_partials(hipStream_t s, int dim, int64_t N, const double *xyz, double *partials, int nblk);
+hipError_t launch_bin_nodes(hipStream_t s, const CellGrid &g, int64_t N, const double *xyz, int32_t *cell_of,
+                            int32_t *cell_count, int32_t *cell_start, int32_t *ids_by_cell, int32_t *cursor,
+                            int32_t *scan_tmp);
+hipError_t launch_coords_by_cell(hipStream_t s, int dim, int64_t N, const double *xyz, const int32_t *ids,
+                                 double *xyz_c);
+hipError_t launch_knn_query(hipStream_t s, const CellGrid &g, int64_t N, const double *xyz, const double *xyz_c,
+                            const int32_t *cell_of, const int32_t *cell_start, const int32_t *ids_by_cell,
+                            int32_t n_uniform, const int16_t *n_per_node, int32_t n_max, double ball_coef,
+                            double margin, int32_t *sten, int16_t *nrow_out, DevStatus *status);
+
+// ---------------------------------------------------------------- weights
+int weights_small_limit();
+int weights_mid_limit();
+int weights_grid(int S_small, int S_mid, int S_large, int panel);
+size_t weights_item_bytes();
+void weights_make_item(void *dst, int kind, int count, int64_t first);
+hipError_t launch_weights_items(hipStream_t s, int dim, int64_t N, const double *xyz, const int32_t *sten,
+                                const int16_t *nrow, int32_t n_max, const int32_t *rows, const int8_t *mrow,
+                                double *w_out, double *scratch, int64_t slab, int panel, DevStatus *status,
+                                const void *items, int64_t nitems, int32_t *counter, int S_small, int S_mid,
+                                int S_large, int grid, size_t *lds_used);
+
+// ---------------------------------------------------------------- sweep family
+hipError_t launch_pack_ell(hipStream_t s, int64_t N_int, int32_t n_max, const int32_t *perm, const int32_t *iperm,
+                           const int32_t *sten, const int16_t *nrow, const double *w_can, const Ell &e);
+hipError_t launch_sweep_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
+                            const double *u_old, double *u_new, double dt, unsigned long long *res_slot);
+hipError_t launch_sweep_f32(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const float *r,
+                            const float *e_old, float *e_new, float dt);
+hipError_t launch_apply_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *u,
+                            double *Lu, const double *f, unsigned long long *res_slot);
+hipError_t launch_outer_residual(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
+                                 const double *u, float *r32, float *e0, unsigned long long *res_slot);
+hipError_t launch_add_correction(hipStream_t s, int64_t N_int, double *u, const float *e);
+hipError_t launch_err_norm(hipStream_t s, int64_t N, const double *u, const double *uref, double *partials,
+                           int nblk, unsigned long long *max_slot);
+hipError_t launch_sum_partials(hipStream_t s, const double *partials, int n, double *out);
+hipError_t launch_transpose_scatter(hipStream_t s, const Ell &e, int64_t N_int, const double *v, double *out);
+hipError_t launch_adjoint_update(hipStream_t s, int64_t N_int, double dt, double *lam, double *acc, double *tmp);
+hipError_t launch_gather(hipStream_t s, int64_t n, const int32_t *perm, const double *src, double *dst);
+hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *perm, const double *src, double *dst);
+hipError_t launch_fill_f64(hipStream_t s, int64_t n, double v, double *p);
+hipError_t launch_fill_f32(hipStream_t s, int64_t n, float v, float *p);
+hipError_t launch_fill_u64(hipStream_t s, int64_t n, unsigned long long v, unsigned long long *p);
+hipError_t launch_scale_interior(hipStream_t s, int64_t N, int64_t N_int, double a, const double *src, double *dst);
+
+}  // namespace rbf

@@ -1,0 +1,83 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol that
+include/rbf.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "rbf.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rbf_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2502_12878_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_2502_12878_amd import build
+        build.build()
+    return _abi.lib()
+
+
+def test_header_declares_the_paper_verbs():
+    names = _declared()
+    for verb in ("rbf_build_nodes", "rbf_build_stencils", "rbf_compute_weights", "rbf_iterate"):
+        assert verb in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2502_12878_amd import _abi
+    names = _declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _abi.SIGNATURES, f"{name} has no Python binding"
+
+
+def test_status_strings(lib):
+    assert lib.rbf_status_string(0) == b"ok"
+    assert lib.rbf_status_string(3) == b"singular local system"
+    assert lib.rbf_status_string(99) == b"unknown status"
+    assert lib.rbf_version().startswith(b"rbf-mi355x")
+
+
+def test_null_handle_rejected(lib):
+    assert lib.rbf_build_nodes(None, 2, 10, 0.3, 0, None, None) == 1
+    assert lib.rbf_set_nodes(None, 2, 10, None, None) == 1
+    assert lib.rbf_build_stencils(None, 12, None) == 1
+    assert lib.rbf_compute_weights(None, 2, None, 0) == 1
+    assert lib.rbf_iterate(None, None, None, None, None) == 1
+    assert lib.rbf_destroy(None) == 1
+    assert lib.rbf_last_error(None) == b"null handle"
+
+
+def test_create_without_device_fails_cleanly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    h = C.c_void_p()
+    assert lib.rbf_create(C.byref(h), 0, None, None) == 1
+    assert not h.value
+
+
+def test_iter_struct_layout_matches_header():
+    """Field order and sizes of the two structs as the header declares them."""
+    from paper_2502_12878_amd import _abi
+    text = open(HEADER).read()
+    for cls, cname in ((_abi.rbf_iter_params, "rbf_iter_params"), (_abi.rbf_iter_report, "rbf_iter_report")):
+        body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + ";", text).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        fields = re.findall(r"\b(\w+)\s*;", body)
+        assert [f for f, _ in cls._fields_] == [f.replace("*", "") for f in fields]
+
+
+def test_package_import_does_not_need_a_gpu():
+    import paper_2502_12878_amd as pkg
+    assert hasattr(pkg, "Problem") and hasattr(pkg, "SolveK")

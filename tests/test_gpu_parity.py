@@ -1,0 +1,312 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded
+inputs.  Bars: node coordinates and supports bit-exact; weights within 1e-10
+relative per row; FP64 iterates within 1e-11 relative; status codes equal."""
+import numpy as np
+import pytest
+
+import oracle
+import rbf_inputs as ri
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    return torch
+
+
+def _problem():
+    from paper_2502_12878_amd import Problem
+    return Problem(0)
+
+
+def _rel_rows(a, b):
+    scale = np.abs(b).max(axis=1) + 1e-300
+    return (np.abs(a - b).max(axis=1) / scale).max()
+
+
+@pytest.mark.parametrize("dim,side,seed,jit", [(2, 100, 0, 0.3), (3, 37, 1, 0.3), (1, 77, 5, 0.3), (3, 9, 2, 0.0)])
+def test_nodes_bitwise(dim, side, seed, jit):
+    p = _problem()
+    xyz, typ = p.build_nodes(dim, side, jit, seed)
+    xr, tr = ri.jittered_grid(dim, side, jit, seed)
+    assert np.array_equal(xyz.cpu().numpy(), xr)
+    assert np.array_equal(typ.cpu().numpy(), tr)
+
+
+KNN_CASES = [(2, 41, 12, 3), (2, 30, 31, 4), (3, 17, 20, 5), (3, 15, 70, 6), (3, 13, 168, 7), (1, 90, 5, 8),
+             (2, 9, 13, None), (3, 7, 27, None)]
+
+
+@pytest.mark.parametrize("dim,side,n,seed", KNN_CASES)
+def test_supports_exact(dim, side, n, seed):
+    jit = 0.0 if seed is None else 0.3
+    xyz, typ = ri.jittered_grid(dim, side, jit, seed or 0)
+    p = _problem()
+    p.set_nodes(xyz, typ)
+    p.build_stencils(n)
+    got = p.get_stencils()
+    ref = oracle.knn(xyz, n)
+    assert np.array_equal(got, ref)
+
+
+def test_supports_per_node_sizes():
+    xyz, typ = ri.jittered_grid(3, 14, 0.3, 9)
+    m, n = ri.order_bands(3, xyz, typ, ri.grid_spacing(14), inner=2.0, outer=4.0)
+    p = _problem()
+    p.set_nodes(xyz, typ)
+    p.build_stencils(n_per_node=n)
+    got = p.get_stencils()
+    nmax = int(n.max())
+    for nn in np.unique(n):
+        rows = np.nonzero(n == nn)[0]
+        ref = oracle.knn(xyz, int(nn), rows)
+        assert np.array_equal(got[rows, :nn], ref)
+        assert (got[rows, nn:] == -1).all()
+    assert got.shape[1] == nmax
+
+
+WEIGHT_CASES = [(2, 30, 2, 12), (2, 20, 4, 30), (2, 22, 6, 56), (3, 12, 2, 20), (3, 11, 4, 70), (3, 10, 6, 168),
+                (1, 40, 4, 10)]
+
+
+@pytest.mark.parametrize("dim,side,m,n", WEIGHT_CASES)
+def test_weights_match_oracle(dim, side, m, n):
+    xyz, typ = ri.jittered_grid(dim, side, 0.3, 10 + m)
+    p = _problem()
+    p.set_nodes(xyz, typ)
+    p.build_stencils(n)
+    p.compute_weights(m)
+    idx, w = oracle.setup(xyz, typ, n, m=m)
+    assert np.array_equal(p.get_stencils(), idx)
+    wg = p.get_weights()
+    I = typ == 0
+    rel = _rel_rows(wg[I], w[I])
+    print(f"dim={dim} m={m} n={n}: max row-relative weight difference {rel:.2e}, "
+          f"bitwise equal rows {np.mean((wg[I] == w[I]).all(axis=1)):.3f}")
+    assert rel <= 1e-10
+    assert (wg[~I] == 0).all()
+
+
+def test_weights_mixed_orders_one_launch():
+    """Per-node orders (2 near the boundary, 4 and 6 inside) in one launch."""
+    side = 14
+    xyz, typ = ri.jittered_grid(3, side, 0.3, 3)
+    m, n = ri.order_bands(3, xyz, typ, ri.grid_spacing(side), inner=2.0, outer=4.0)
+    assert set(np.unique(m[typ == 0])) == {2, 4, 6}
+    p = _problem()
+    p.set_nodes(xyz, typ)
+    p.build_stencils(n_per_node=n)
+    p.compute_weights(m_per_node=m)
+    idx, w = oracle.setup(xyz, typ, 0, n_row=n, m_row=m)
+    wg = p.get_weights()
+    I = typ == 0
+    assert _rel_rows(wg[I], w[I]) <= 1e-10
+
+
+def _setup_pair(dim, side, m, n, seed, keep_fp32=False, alpha=0.15):
+    import torch
+    xyz, typ = ri.jittered_grid(dim, side, 0.3, seed)
+    idx, w = oracle.setup(xyz, typ, n, m=m)
+    u_ex, f, g, u0 = ri.manufactured(dim, xyz, typ)
+    h = ri.grid_spacing(side)
+    dt = alpha * h * h / (2 * dim)
+    p = _problem()
+    p.set_nodes(xyz, typ)
+    p.set_stencils(idx)
+    p.set_weights(w, keep_fp32=keep_fp32)
+    op = oracle.Operator(typ, idx, w)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    return dict(p=p, op=op, xyz=xyz, typ=typ, idx=idx, w=w, f=f, g=g, u0=u0, u_ex=u_ex, dt=dt, dev=dev, h=h)
+
+
+@pytest.mark.parametrize("dim,side,m,n,steps,chunk", [(2, 45, 2, 12, 1000, 250), (3, 14, 4, 70, 400, 100),
+                                                      (3, 11, 6, 168, 301, 100)])
+def test_fixed_steps_match_oracle(dim, side, m, n, steps, chunk):
+    s = _setup_pair(dim, side, m, n, 30 + m)
+    u = s["dev"](s["u0"])
+    st, rep = s["p"].iterate(s["dev"](s["f"]), u, s["dt"], steps, 0.0, chunk)
+    uo, rep_o, st_o = s["op"].iterate(s["f"], s["dt"], s["u0"], steps, 0.0, chunk)
+    assert st == st_o == 0 and rep["steps"] == rep_o["steps"] == steps
+    ug = u.cpu().numpy()
+    assert np.abs(ug - uo).max() <= 1e-11 * np.abs(uo).max()
+    B = s["typ"] == 1
+    assert np.array_equal(ug[B], s["g"][B])
+    assert abs(rep["res_final"] - rep_o["res_final"]) <= 1e-9 * rep_o["res_final"]
+    assert abs(rep["res0"] - rep_o["res0"]) <= 1e-12 * rep_o["res0"]
+    assert rep["fnorm"] == rep_o["fnorm"]
+
+
+def test_apply_and_residual_match_oracle():
+    s = _setup_pair(3, 13, 4, 70, 3)
+    rng = np.random.default_rng(0)
+    u = rng.standard_normal(len(s["typ"]))
+    Lg = s["p"].apply(s["dev"](u)).cpu().numpy()
+    Lo = s["op"].apply(u)
+    assert np.abs(Lg - Lo).max() <= 1e-12 * np.abs(Lo).max()
+    assert (Lg[s["typ"] == 1] == 0).all()
+    r = s["p"].residual(s["dev"](s["f"]), s["dev"](u))
+    assert abs(r - s["op"].residual(s["f"], u)) <= 1e-12 * abs(r)
+
+
+def test_converges_at_same_chunk_as_oracle():
+    s = _setup_pair(2, 25, 2, 12, 4)
+    u = s["dev"](s["u0"])
+    st, rep = s["p"].iterate(s["dev"](s["f"]), u, s["dt"], 500000, 1e-9, 200)
+    uo, rep_o, st_o = s["op"].iterate(s["f"], s["dt"], s["u0"], 500000, 1e-9, 200)
+    assert st == st_o == 0 and rep["converged"] == 1
+    assert rep["steps"] == rep_o["steps"]
+    assert np.abs(u.cpu().numpy() - uo).max() <= 1e-11 * np.abs(uo).max()
+
+
+def test_status_codes_match_oracle():
+    s = _setup_pair(2, 21, 2, 12, 5)
+    p, op, dev = s["p"], s["op"], s["dev"]
+    from paper_2502_12878_amd import RBF_EDIVERGED, RBF_ENOTCONVERGED
+    # divergence at a large step, at the same chunk
+    dt_big = 3.0 * s["h"] ** 2 / 4
+    u = dev(s["u0"])
+    st, rep = p.iterate(dev(s["f"]), u, dt_big, 5000, 0.0, 100)
+    _, rep_o, st_o = op.iterate(s["f"], dt_big, s["u0"], 5000, 0.0, 100)
+    assert st == st_o == RBF_EDIVERGED and rep["diverged_step"] == rep_o["diverged_step"]
+    # NaN in f: diverged at step 0
+    fn = s["f"].copy()
+    fn[np.nonzero(s["typ"] == 0)[0][7]] = np.nan
+    st, rep = p.iterate(dev(fn), dev(s["u0"]), s["dt"], 100, 1e-8, 10)
+    assert st == RBF_EDIVERGED and rep["diverged_step"] == 0 and rep["steps"] == 0
+    # max_steps with a tolerance: not converged
+    st, rep = p.iterate(dev(s["f"]), dev(s["u0"]), s["dt"], 300, 1e-12, 100)
+    _, rep_o, st_o = op.iterate(s["f"], s["dt"], s["u0"], 300, 1e-12, 100)
+    assert st == st_o == RBF_ENOTCONVERGED and rep["steps"] == 300
+
+
+def test_error_target_stops_run():
+    s = _setup_pair(2, 25, 2, 12, 6)
+    u = s["dev"](s["u0"])
+    ref = s["dev"](s["u_ex"])
+    st, rep = s["p"].iterate(s["dev"](s["f"]), u, s["dt"], 10 ** 6, 0.0, 100, u_ref=ref, err_target=0.02)
+    assert st == 0 and rep["err_met"] == 1
+    ug = u.cpu().numpy()
+    assert abs(np.abs(ug - s["u_ex"]).max() - rep["err_inf"]) <= 1e-15
+    assert abs(np.abs(ug - s["u_ex"]).mean() - rep["err_mean_abs"]) <= 1e-15
+    assert rep["err_inf"] <= 0.02
+
+
+def test_mixed_precision_matches_oracle():
+    s = _setup_pair(3, 12, 4, 70, 7, keep_fp32=True)
+    from paper_2502_12878_amd import RBF_MODE_MIXED
+    u = s["dev"](s["u0"])
+    st, rep = s["p"].iterate(s["dev"](s["f"]), u, s["dt"], 3 * 200, 0.0, 1, mode=RBF_MODE_MIXED, inner_steps=200)
+    uo, passes, _ = s["op"].mixed(s["f"], s["dt"], s["u0"], 200, 3)
+    assert st == 0 and rep["steps"] == 600 and passes == 3
+    corr = np.abs(uo - s["u0"]).max()
+    assert np.abs(u.cpu().numpy() - uo).max() <= 1e-5 * corr
+
+
+def test_transpose_and_adjoint_match_oracle():
+    s = _setup_pair(2, 19, 2, 12, 8)
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(len(s["typ"]))
+    tg = s["p"].apply_transpose(s["dev"](v)).cpu().numpy()
+    to = s["op"].apply_transpose(v)
+    assert np.abs(tg - to).max() <= 1e-12 * np.abs(to).max()
+    K, every = 300, 100
+    gK = rng.standard_normal(len(s["typ"]))
+    gg = s["p"].adjoint_f(s["dev"](gK), K, every, s["dt"]).cpu().numpy()
+    go = s["op"].adjoint_f(s["dt"], K, gK)
+    assert np.abs(gg - go).max() <= 1e-11 * np.abs(go).max()
+
+
+def test_forward_checkpoints_resume_bitwise():
+    s = _setup_pair(2, 19, 2, 12, 9)
+    p, dev = s["p"], s["dev"]
+    ck, uK = p.forward_ckpt(dev(s["f"]), dev(s["u0"]), 400, 100, s["dt"])
+    assert np.array_equal(ck[0].cpu().numpy(), s["u0"])
+    assert np.array_equal(ck[-1].cpu().numpy(), uK.cpu().numpy())
+    # restarting from checkpoint 2 reproduces checkpoint 4 bit for bit
+    _, u2 = p.forward_ckpt(dev(s["f"]), ck[2], 200, 100, s["dt"], keep_checkpoints=False)
+    assert np.array_equal(u2.cpu().numpy(), uK.cpu().numpy())
+    uo, _, _ = s["op"].iterate(s["f"], s["dt"], s["u0"], 400, 0.0, 400)
+    assert np.abs(uK.cpu().numpy() - uo).max() <= 1e-11 * np.abs(uo).max()
+
+
+def test_autograd_gradient_matches_central_differences(torch):
+    from paper_2502_12878_amd import SolveK
+    s = _setup_pair(2, 13, 2, 12, 10)
+    p, dev, typ, xyz = s["p"], s["dev"], s["typ"], s["xyz"]
+    I = torch.tensor(typ == 0, device="cuda")
+    K, every = 200, 50
+    zero = dev(np.zeros(len(typ)))
+    f = dev(np.where(typ == 0, ri.gaussian_field(2, xyz, 104), 0.0)).requires_grad_(True)
+    ft = dev(np.where(typ == 0, ri.gaussian_field(2, xyz, 204), 0.0)) * 0.1 + f.detach()
+    u_t = SolveK.apply(ft, p, zero, K, every, s["dt"]).detach()
+
+    def J(ff):
+        d = (SolveK.apply(ff, p, zero, K, every, s["dt"]) - u_t)[I]
+        return 0.5 * (d * d).sum()
+
+    loss = J(f)
+    loss.backward()
+    g = f.grad.detach()
+    eps = 1e-2 * f.detach().abs().max()
+    with torch.no_grad():
+        for j in range(8):
+            v = dev(np.where(typ == 0, ri.gaussian_field(2, xyz, 304 + j), 0.0))
+            v = v / v.abs().max()
+            fd = (J(f.detach() + eps * v) - J(f.detach() - eps * v)) / (2 * eps)
+            assert abs(float((g * v).sum() - fd)) <= 1e-6 * abs(float(fd))
+
+
+def test_gradcheck_tiny(torch):
+    from paper_2502_12878_amd import SolveK
+    s = _setup_pair(3, 6, 2, 20, 11)
+    p, dev = s["p"], s["dev"]
+    zero = dev(np.zeros(len(s["typ"])))
+    f = dev(np.random.default_rng(4).standard_normal(len(s["typ"])) * (s["typ"] == 0)).requires_grad_(True)
+    mask = torch.tensor(s["typ"] == 0, device="cuda", dtype=torch.float64)
+    fn = lambda ff: SolveK.apply(ff * mask, p, zero, 20, 10, s["dt"])
+    assert torch.autograd.gradcheck(fn, (f,), eps=1e-6, atol=1e-8, rtol=1e-6, nondet_tol=1e-12)
+
+
+def test_singular_supports_reported():
+    from paper_2502_12878_amd import RbfError, RBF_ESINGULAR
+    xyz, typ = ri.jittered_grid(2, 15, 0.3, 12)
+    p = _problem()
+    p.set_nodes(xyz, typ)
+    p.build_stencils(5)  # fewer nodes than the 6 monomials of order 2
+    with pytest.raises(RbfError) as ei:
+        p.compute_weights(2)
+    assert ei.value.status == RBF_ESINGULAR
+    first_interior = int(np.nonzero(typ == 0)[0][0])
+    _, _, st, bad = oracle.weights(xyz, oracle.knn(xyz, 5, [first_interior]), [first_interior], m=2,
+                                   raise_on_singular=False)
+    assert st == 3 and f"node {bad}" in str(ei.value)
+    # duplicate nodes
+    xd = xyz.copy()
+    xd[:, 40] = xd[:, 41]
+    p.set_nodes(xd, typ)
+    p.build_stencils(12)
+    with pytest.raises(RbfError) as ei:
+        p.compute_weights(2)
+    assert ei.value.status == RBF_ESINGULAR
+
+
+def test_invalid_arguments_rejected():
+    from paper_2502_12878_amd import RbfError, RBF_EINVAL
+    p = _problem()
+    with pytest.raises(RbfError) as ei:
+        p.build_stencils(12)
+    assert ei.value.status == RBF_EINVAL
+    xyz, typ = ri.jittered_grid(2, 5, 0.3, 0)
+    p.set_nodes(xyz, typ)
+    for bad_n in (0, 26, 300):
+        with pytest.raises(RbfError):
+            p.build_stencils(bad_n)
+    p.build_stencils(12)
+    with pytest.raises(RbfError):
+        p.compute_weights(7)
+    import torch
+    u = torch.zeros(25, dtype=torch.float64, device="cuda")
+    with pytest.raises(RbfError):
+        p.iterate(u, u, 1e-3, 10)  # no weights yet
