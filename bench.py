@@ -1,0 +1,231 @@
+"""Benchmark of the explicit RBF-FD Poisson iteration on one MI355X.
+
+Workload: 3D unit cube, 100^3 jittered grid (jitter 0.3h, seed 1), Dirichlet
+data from u = sin(pi x) sin(pi y) sin(pi z), PHS r^3 + monomials of order m
+with n = 2*C(m+3, 3) nearest nodes (m = 4, n = 70 is the headline; m = 2 and 6
+are reported beside it).  One step = one explicit sweep
+u <- u + dt (L_h u - f) over all interior nodes (with the fused Dirichlet rows
+and max-residual reduction), run by the library in HIP-graph chunks.
+
+Prints one JSON line: node-updates/s (value), HBM GB/s of the sweep kernel
+against the 8 TB/s peak (roofline), setup times, time to L-inf error 1e-6
+for FP64 vs FP32+FP64 refinement, and the CPU oracle's OpenMP sweep as a
+baseline.  Inputs are synthetic and seeded; they are in HBM before timing.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def sweep_source_hash():
+    with open(os.path.join(ROOT, "paper_2502_12878_amd", "csrc", "k_sweep.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def stored_traffic(key):
+    """HBM bytes per sweep launch measured with rocprofv3 counters, if they
+    were taken on the current sweep source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = d.get(key)
+    if not e or e.get("kernel_source") != sweep_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def setup_problem(m, keep_fp32=False, autotune=True):
+    import torch
+
+    import rbf_inputs as ri
+    from paper_2502_12878_amd import Problem
+
+    wl = ri.workload("cube1M", m=m)
+    p = Problem(0)
+    t0 = time.perf_counter()
+    xyz, typ = p.build_nodes(wl.dim, wl.side, wl.jitter, wl.seed)
+    p.set_nodes(xyz, typ)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    p.build_stencils(wl.n)
+    t2 = time.perf_counter()
+    p.compute_weights(wl.m, keep_fp32=keep_fp32)
+    t3 = time.perf_counter()
+    if autotune:
+        p.autotune()
+    # manufactured problem (the generator's coordinates equal the GPU's bit for bit)
+    xyz_h, typ_h = wl.nodes()
+    u_ex, f, g, u0 = ri.manufactured(wl.dim, xyz_h, typ_h)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    return dict(p=p, wl=wl, f=dev(f), u0=dev(u0), u_ex=dev(u_ex), typ=typ_h, f_h=f, u0_h=u0,
+                setup={"nodes_s": t1 - t0, "stencils_s": t2 - t1, "weights_s": t3 - t2})
+
+
+def time_sweeps(s, steps, warmup, chunk=500):
+    import torch
+    p, wl = s["p"], s["wl"]
+    u = s["u0"].clone()
+    st, _ = p.iterate(s["f"], u, wl.dt, warmup, 0.0, min(chunk, max(1, warmup)))
+    assert st == 0, st
+    u = s["u0"].clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, rep = p.iterate(s["f"], u, wl.dt, steps, 0.0, chunk)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert st == 0, (st, rep)
+    per_sweep, nsw = p.last_sweep_time()
+    return t1 - t0, per_sweep, nsw, rep
+
+
+def time_to_error(s, target, inner=500, max_steps=2_000_000):
+    """Steps and device time until max|u - u_exact| <= target, plain FP64 vs
+    FP32 inner sweeps with FP64 outer correction (checked every `inner` steps
+    in both modes)."""
+    import torch
+    from paper_2502_12878_amd import RBF_MODE_FP64, RBF_MODE_MIXED
+    p, wl = s["p"], s["wl"]
+    out = {}
+    for name, mode in (("fp64", RBF_MODE_FP64), ("fp32_refine", RBF_MODE_MIXED)):
+        u = s["u0"].clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, rep = p.iterate(s["f"], u, wl.dt, max_steps, 0.0, inner, mode=mode, inner_steps=inner,
+                            u_ref=s["u_ex"], err_target=target)
+        torch.cuda.synchronize()
+        out[name] = {"status": st, "steps": rep["steps"], "wall_s": round(time.perf_counter() - t0, 3),
+                     "device_s": round(rep["seconds"], 3), "err_inf": rep["err_inf"],
+                     "err_mean_abs": rep["err_mean_abs"], "reached": bool(rep["err_met"])}
+    if out["fp64"]["reached"] and out["fp32_refine"]["reached"]:
+        out["speedup_fp32_refine"] = round(out["fp64"]["wall_s"] / out["fp32_refine"]["wall_s"], 3)
+    return out
+
+
+def cpu_baseline(budget_s=10.0):
+    """The oracle's OpenMP sweep on a bounded sample of the workload: the same
+    generator and parameters (3D, jitter 0.3h, seed 1, m = 4, n = 70) on a
+    30^3 grid, whose supports and weights the oracle itself can build in
+    seconds; timed for ~budget_s after an untimed setup."""
+    import numpy as np
+
+    import oracle
+    import rbf_inputs as ri
+    side, m, n = 30, 4, 70
+    xyz, typ = ri.jittered_grid(3, side, 0.3, 1)
+    idx, w = oracle.setup(xyz, typ, n, m=m)
+    u_ex, f, g, u0 = ri.manufactured(3, xyz, typ)
+    h = ri.grid_spacing(side)
+    dt = 0.15 * h * h / 6
+    op = oracle.Operator(typ, idx, w)
+    threads = len(os.sched_getaffinity(0))
+    a, b = u0.copy(), u0.copy()
+    nint = int((typ == 0).sum())
+    res = {}
+    for nt in (threads, 1):
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            op.sweep_omp(f, dt, a, b, nt)
+            a, b = b, a
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= (budget_s if nt == threads else budget_s / 4):
+                break
+        res[nt] = nint * steps / el
+    return {"value": res[threads], "unit": "node-updates/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": res[1],
+            "sample": f"oracle OpenMP sweep (row-parallel for) on the same workload generator at 30^3 nodes "
+                      f"({nint} interior rows, m=4, n=70), {budget_s:.0f} s window after an untimed oracle setup"}
+
+
+def calibrate_copy(nbytes=1 << 30, reps=10):
+    """A plain device copy of known size, for scaling rocprofv3 FETCH_SIZE /
+    WRITE_SIZE readings to bytes."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read_per_launch": nbytes, "bytes_written_per_launch": nbytes,
+                      "launches": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--orders", default="4,2,6", help="augmentation orders; the first is the headline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-tte", action="store_true", help="skip the time-to-error comparison")
+    ap.add_argument("--tte-target", type=float, default=1e-6)
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    os.environ.setdefault("RBF_AUTOTUNE_CACHE", os.path.join(ROOT, "_build", "autotune.json"))
+    os.makedirs(os.path.join(ROOT, "_build"), exist_ok=True)
+    import torch
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    orders = [int(x) for x in args.orders.split(",") if x]
+    per_order = {}
+    head = None
+    for i, m in enumerate(orders):
+        s = setup_problem(m, keep_fp32=(i == 0 and not args.no_tte))
+        wl = s["wl"]
+        nint = int((s["typ"] == 0).sum())
+        wall, per_sweep, nsw, rep = time_sweeps(s, args.steps, args.warmup)
+        bytes_per_update = 12 * wl.n + 24
+        alg_bytes = bytes_per_update * nint
+        entry = {"m": m, "n": wl.n, "interior_nodes": nint, "node_updates_per_s": nint * args.steps / wall,
+                 "ms_per_step": 1e3 * wall / args.steps, "kernel_ms_per_sweep": 1e3 * per_sweep,
+                 "alg_bytes_per_update": bytes_per_update, "alg_GBps": alg_bytes / per_sweep / 1e9,
+                 "hbm_frac": alg_bytes / per_sweep / 1e9 / PEAK_HBM_GBS, "res_final": rep["res_final"],
+                 "setup": {k: round(v, 3) for k, v in s["setup"].items()}}
+        per_order[m] = entry
+        if i == 0:
+            head = (s, entry, wall, per_sweep, nsw)
+        else:
+            s["p"].close()
+    s, entry, wall, per_sweep, nsw = head
+    wl = s["wl"]
+    key = f"sweep_f64|cube1M|m{wl.m}"
+    traffic = stored_traffic(key)
+    alg_bytes = entry["alg_bytes_per_update"] * entry["interior_nodes"]
+    roofline = {"bound": "hbm", "achieved": round(alg_bytes / per_sweep / 1e9, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(alg_bytes / per_sweep / 1e9 / PEAK_HBM_GBS, 4),
+                "traffic": traffic, "kernel": "k_sweep_f64", "alg_bytes_per_launch": alg_bytes,
+                "avg_launch_ms": round(1e3 * per_sweep, 5), "launches_timed": nsw}
+    tte = None if args.no_tte else time_to_error(s, args.tte_target)
+    cpu = None if args.no_cpu else cpu_baseline()
+    out = {"metric": "sweep node-updates/s + HBM GB/s; time to L-inf err 1e-6, FP32+refine vs FP64",
+           "value": entry["node_updates_per_s"], "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": entry["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"cube1M: 3D 100^3 jittered grid (seed 1), m={wl.m}, n={wl.n}, "
+                                  f"dt={wl.alpha}*h^2/6, FP64 explicit sweep",
+                      "interior_nodes": entry["interior_nodes"], "parallelism": "single GPU"},
+           "roofline": roofline, "cpu_baseline": cpu,
+           "orders": {str(k): v for k, v in per_order.items()}, "time_to_error": tte,
+           "device": torch.cuda.get_device_name(0)}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
