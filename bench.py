@@ -149,6 +149,28 @@ def cpu_baseline(budget_s=10.0):
                       f"({nint} interior rows, m=4, n=70), {budget_s:.0f} s window after an untimed oracle setup"}
 
 
+def stream_ceiling(nbytes=1 << 30, reps=20):
+    """Achievable HBM rates on this device for context: a 1 GiB device copy
+    (read + write) and a 1 GiB read-only sum, timed with events."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    out = {}
+    for name, fn, moved in (("copy", lambda: y.copy_(x), 2 * nbytes), ("read", lambda: x.sum(), nbytes)):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{name}_GBps"] = round(moved * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def calibrate_copy(nbytes=1 << 30, reps=10):
     """A plain device copy of known size, for scaling rocprofv3 FETCH_SIZE /
     WRITE_SIZE readings to bytes."""
@@ -223,6 +245,7 @@ def main():
                       "interior_nodes": entry["interior_nodes"], "parallelism": "single GPU"},
            "roofline": roofline, "cpu_baseline": cpu,
            "orders": {str(k): v for k, v in per_order.items()}, "time_to_error": tte,
+           "stream_ceiling": stream_ceiling(), "ell_layout": int(os.environ.get("RBF_ELL_LAYOUT", "1")),
            "device": torch.cuda.get_device_name(0)}
     print(json.dumps(out))
 

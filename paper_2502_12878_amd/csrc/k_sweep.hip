@@ -57,36 +57,103 @@ __device__ __forceinline__ void block_max_to_slot(unsigned long long bits, unsig
     }
 }
 
-// sum_k w[k] * x[idx[k]] over one row's packed entries (k < len).
-template <typename T, int U>
-__device__ __forceinline__ T ell_row_dot(const int32_t *__restrict__ idx, const T *__restrict__ w,
-                                         const T *__restrict__ x, int64_t base, int len) {
-    T acc = T(0);
-    int k = 0;
-    for (; k + U <= len; k += U) {
-        int32_t j[U];
-        T ww[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-            j[q] = ld_stream(idx + base + (int64_t)(k + q) * kSlice);
-            ww[q] = ld_stream(w + base + (int64_t)(k + q) * kSlice);
-        }
-        T xx[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) xx[q] = x[j[q]];
-#pragma unroll
-        for (int q = 0; q < U; ++q) acc = fma(ww[q], xx[q], acc);
-    }
-    for (; k < len; ++k) {
-        const int32_t j = ld_stream(idx + base + (int64_t)k * kSlice);
-        const T ww = ld_stream(w + base + (int64_t)k * kSlice);
-        acc = fma(ww, x[j], acc);
-    }
-    return acc;
+// Element position of support entry k of `lane` in a slice starting at base.
+//   layout 0: base + 64 k + lane (one dword / qword per lane per entry)
+//   layout 1: slice length padded to even; entry pairs interleaved,
+//             base + 128 (k / 2) + 2 lane + k % 2, for indices and weights
+//             alike: per 2 entries one 8-byte index vector and one 16-byte
+//             FP64 weight vector per lane (a wavefront load covers 512 B /
+//             1 KB contiguous).
+__host__ __device__ __forceinline__ int64_t ell_pos(int layout, int64_t base, int k, int lane) {
+    if (layout == 0) return base + (int64_t)k * kSlice + lane;
+    return base + (int64_t)(k >> 1) * (2 * kSlice) + 2 * lane + (k & 1);
 }
 
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> { typedef f64x2 type; };
+template <>
+struct Vec2<float> { typedef f32x2 type; };
+
+// sum_k w[k] * x[idx[k]] over one row's packed entries (k < len), layout 0.
+template <typename T, int U, int LAYOUT>
+struct RowDot {
+    __device__ static __forceinline__ T run(const int32_t *__restrict__ idx, const T *__restrict__ w,
+                                            const T *__restrict__ x, int64_t base, int lane, int len) {
+        T acc = T(0);
+        int k = 0;
+        base += lane;
+        for (; k + U <= len; k += U) {
+            int32_t j[U];
+            T ww[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                j[q] = ld_stream(idx + base + (int64_t)(k + q) * kSlice);
+                ww[q] = ld_stream(w + base + (int64_t)(k + q) * kSlice);
+            }
+            T xx[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) xx[q] = x[j[q]];
+#pragma unroll
+            for (int q = 0; q < U; ++q) acc = fma(ww[q], xx[q], acc);
+        }
+        for (; k < len; ++k) {
+            const int32_t j = ld_stream(idx + base + (int64_t)k * kSlice);
+            const T ww = ld_stream(w + base + (int64_t)k * kSlice);
+            acc = fma(ww, x[j], acc);
+        }
+        return acc;
+    }
+};
+
+// Layout 1: pairs of entries as vectors; len is even.
+template <typename T, int U>
+struct RowDot<T, U, 1> {
+    __device__ static __forceinline__ T run(const int32_t *__restrict__ idx, const T *__restrict__ w,
+                                            const T *__restrict__ x, int64_t base, int lane, int len) {
+        typedef typename Vec2<T>::type V;
+        constexpr int P = U / 2;
+        T acc = T(0);
+        const i32x2 *ip = (const i32x2 *)(idx + base) + lane;
+        const V *wp = (const V *)(w + base) + lane;
+        int k = 0;
+        for (; k + U <= len; k += U) {
+            i32x2 j[P];
+            V ww[P];
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                j[q] = __builtin_nontemporal_load(ip + ((k >> 1) + q) * kSlice);
+                ww[q] = __builtin_nontemporal_load(wp + ((k >> 1) + q) * kSlice);
+            }
+            T xx[U];
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                xx[2 * q] = x[j[q].x];
+                xx[2 * q + 1] = x[j[q].y];
+            }
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                acc = fma(ww[q].x, xx[2 * q], acc);
+                acc = fma(ww[q].y, xx[2 * q + 1], acc);
+            }
+        }
+        for (; k < len; k += 2) {
+            const i32x2 j = __builtin_nontemporal_load(ip + (k >> 1) * kSlice);
+            const V ww = __builtin_nontemporal_load(wp + (k >> 1) * kSlice);
+            acc = fma(ww.x, x[j.x], acc);
+            acc = fma(ww.y, x[j.y], acc);
+        }
+        return acc;
+    }
+};
+
 // One explicit step on every interior row; optionally max |rho| into slot.
-template <int WAVES, int U, bool REDUCE>
+template <int WAVES, int U, int LAYOUT, bool REDUCE>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
     const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ f,
@@ -97,9 +164,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
     const int lane = threadIdx.x & 63;
     unsigned long long bits = 0;
     if (slice < nslices) {
-        const int64_t base = slice_ptr[slice] + lane;
         const int len = slice_len[slice];
-        const double acc = ell_row_dot<double, U>(idx, w, u_old, base, len);
+        const double acc = RowDot<double, U, LAYOUT>::run(idx, w, u_old, slice_ptr[slice], lane, len);
         const int64_t row = slice * kSlice + lane;
         if (row < N_int) {
             const double rho = acc - f[row];
@@ -111,7 +177,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
 }
 
 // FP32 step on the correction: e_new = e + dt (L32 e - r).
-template <int WAVES, int U>
+template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep_f32(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
     const float *__restrict__ w, int64_t nslices, int64_t N_int, const float *__restrict__ r,
@@ -120,15 +186,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f32(
     const int64_t slice = blk * WAVES + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (slice >= nslices) return;
-    const int64_t base = slice_ptr[slice] + lane;
     const int len = slice_len[slice];
-    const float acc = ell_row_dot<float, U>(idx, w, e_old, base, len);
+    const float acc = RowDot<float, U, LAYOUT>::run(idx, w, e_old, slice_ptr[slice], lane, len);
     const int64_t row = slice * kSlice + lane;
     if (row < N_int) e_new[row] = e_old[row] + dt * (acc - r[row]);
 }
 
 // Lu (and, with f, max |Lu - f| into slot).
-template <int WAVES, int U>
+template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_apply_f64(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
     const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ u,
@@ -138,9 +203,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_apply_f64(
     const int lane = threadIdx.x & 63;
     unsigned long long bits = 0;
     if (slice < nslices) {
-        const int64_t base = slice_ptr[slice] + lane;
         const int len = slice_len[slice];
-        const double acc = ell_row_dot<double, U>(idx, w, u, base, len);
+        const double acc = RowDot<double, U, LAYOUT>::run(idx, w, u, slice_ptr[slice], lane, len);
         const int64_t row = slice * kSlice + lane;
         if (row < N_int) {
             if (Lu) Lu[row] = acc;
@@ -152,7 +216,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_apply_f64(
 
 // Outer residual of the refinement loop: r32 = (float)(f - L64 u); e0 = 0;
 // max |f - L64 u| into slot (the residual of u) when slot is given.
-template <int WAVES, int U>
+template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_outer_residual(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
     const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ f,
@@ -163,9 +227,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_outer_residual(
     const int lane = threadIdx.x & 63;
     unsigned long long bits = 0;
     if (slice < nslices) {
-        const int64_t base = slice_ptr[slice] + lane;
         const int len = slice_len[slice];
-        const double acc = ell_row_dot<double, U>(idx, w, u, base, len);
+        const double acc = RowDot<double, U, LAYOUT>::run(idx, w, u, slice_ptr[slice], lane, len);
         const int64_t row = slice * kSlice + lane;
         if (row < N_int) {
             const double r = f[row] - acc;
@@ -182,18 +245,18 @@ template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_transpose_scatter(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
     const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ v,
-    double *__restrict__ out) {
+    double *__restrict__ out, int layout) {
     const int64_t slice = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (slice >= nslices) return;
     const int64_t row = slice * kSlice + lane;
     if (row >= N_int) return;
     const double vr = v[row];
-    const int64_t base = slice_ptr[slice] + lane;
+    const int64_t base = slice_ptr[slice];
     const int len = slice_len[slice];
     for (int k = 0; k < len; ++k) {
-        const int32_t c = ld_stream(idx + base + (int64_t)k * kSlice);
-        const double ww = ld_stream(w + base + (int64_t)k * kSlice);
+        const int32_t c = ld_stream(idx + ell_pos(layout, base, k, lane));
+        const double ww = ld_stream(w + ell_pos(layout, base, k, lane));
         if (c < N_int && ww != 0.0) unsafeAtomicAdd(out + c, ww * vr);
     }
 }
@@ -246,46 +309,46 @@ __global__ void k_sum_partials(const double *__restrict__ p, int n, double *out)
     if (threadIdx.x == 0) *out = s[0];
 }
 
-// Packed-operator builder: thread per (internal row, slot).  Entry k of
-// canonical row r goes to the position of its rank among the row's internal
+// Packed-operator builder: thread per (internal row, slot k < kmax).  Entry
+// k of canonical row r goes to the slot of its rank among the row's internal
 // column ids; slots past the row's size hold the row itself with weight 0;
 // rows past N_int (tail of the last slice) hold column 0 with weight 0.
-__global__ void k_pack_ell(int64_t N_int, int32_t n_max, int64_t nslices, const int32_t *__restrict__ perm,
-                           const int32_t *__restrict__ iperm, const int32_t *__restrict__ sten,
-                           const int16_t *__restrict__ nrow, const double *__restrict__ w_can,
-                           const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len,
-                           int32_t *__restrict__ idx, double *__restrict__ w, float *__restrict__ w32) {
+__global__ void k_pack_ell(int64_t N_int, int32_t n_max, int32_t kmax, int64_t nslices, int layout,
+                           const int32_t *__restrict__ perm, const int32_t *__restrict__ iperm,
+                           const int32_t *__restrict__ sten, const int16_t *__restrict__ nrow,
+                           const double *__restrict__ w_can, const int64_t *__restrict__ slice_ptr,
+                           const int32_t *__restrict__ slice_len, int32_t *__restrict__ idx, double *__restrict__ w,
+                           float *__restrict__ w32) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t i = t / n_max;
-    const int k = (int)(t - i * n_max);
+    const int64_t i = t / kmax;
+    const int k = (int)(t - i * kmax);
     if (i >= nslices * kSlice) return;
     const int64_t s = i / kSlice;
     const int lane = (int)(i - s * kSlice);
     const int len = slice_len[s];
     if (k >= len) return;
-    const int64_t base = slice_ptr[s] + lane;
-    if (i >= N_int) {
-        idx[base + (int64_t)k * kSlice] = 0;
-        w[base + (int64_t)k * kSlice] = 0.0;
-        if (w32) w32[base + (int64_t)k * kSlice] = 0.0f;
-        return;
+    const int64_t base = slice_ptr[s];
+    int32_t col = 0;
+    double wk = 0.0;
+    int slot = k;
+    if (i < N_int) {
+        const int64_t r = perm[i];
+        const int n = nrow[r];
+        if (k >= n) {
+            col = (int32_t)i;
+        } else {
+            const int32_t *row = sten + r * (int64_t)n_max;
+            col = iperm[row[k]];
+            int rank = 0;
+            for (int q = 0; q < n; ++q) rank += (iperm[row[q]] < col) ? 1 : 0;
+            slot = rank;
+            wk = w_can[r * (int64_t)n_max + k];
+        }
     }
-    const int64_t r = perm[i];
-    const int n = nrow[r];
-    if (k >= n) {
-        idx[base + (int64_t)k * kSlice] = (int32_t)i;
-        w[base + (int64_t)k * kSlice] = 0.0;
-        if (w32) w32[base + (int64_t)k * kSlice] = 0.0f;
-        return;
-    }
-    const int32_t *row = sten + r * (int64_t)n_max;
-    const int32_t key = iperm[row[k]];
-    int rank = 0;
-    for (int q = 0; q < n; ++q) rank += (iperm[row[q]] < key) ? 1 : 0;
-    const double wk = w_can[r * (int64_t)n_max + k];
-    idx[base + (int64_t)rank * kSlice] = key;
-    w[base + (int64_t)rank * kSlice] = wk;
-    if (w32) w32[base + (int64_t)rank * kSlice] = (float)wk;
+    const int64_t pos = ell_pos(layout, base, slot, lane);
+    idx[pos] = col;
+    w[pos] = wk;
+    if (w32) w32[pos] = (float)wk;
 }
 
 __global__ void k_gather(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ src,
@@ -311,11 +374,13 @@ __global__ void k_scale_interior(int64_t N, int64_t N_int, double a, const doubl
 
 inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// Dispatch over the tuned (waves per block, unroll) pairs.
-template <template <int, int> class F, typename... A>
-hipError_t dispatch_shape(const SweepCfg &c, A &&...a) {
-#define RBF_CASE(WV, UN) \
-    if (c.waves_per_block == WV && c.unroll == UN) return F<WV, UN>::run(a...);
+// Dispatch over the tuned (waves per block, unroll, layout) triples.
+template <template <int, int, int> class F, typename... A>
+hipError_t dispatch_shape(const SweepCfg &c, int layout, A &&...a) {
+#define RBF_CASE(WV, UN)                                                  \
+    if (c.waves_per_block == WV && c.unroll == UN) {                      \
+        return layout ? F<WV, UN, 1>::run(a...) : F<WV, UN, 0>::run(a...); \
+    }
     RBF_CASE(2, 4) RBF_CASE(2, 8) RBF_CASE(2, 16)
     RBF_CASE(4, 4) RBF_CASE(4, 8) RBF_CASE(4, 16)
     RBF_CASE(8, 4) RBF_CASE(8, 8) RBF_CASE(8, 16)
@@ -323,46 +388,50 @@ hipError_t dispatch_shape(const SweepCfg &c, A &&...a) {
     return hipErrorInvalidValue;
 }
 
-template <int WV, int UN>
+template <int WV, int UN, int LY>
 struct SweepF64 {
     static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const double *f, const double *uo, double *un,
                           double dt, unsigned long long *slot, int remap) {
+        if (!e.nslices) return hipSuccess;
         const unsigned g = grid1d(e.nslices, WV);
         if (slot)
-            hipLaunchKernelGGL((k_sweep_f64<WV, UN, true>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr, e.slice_len,
-                               e.idx, e.w, e.nslices, N_int, f, uo, un, dt, slot, remap);
+            hipLaunchKernelGGL((k_sweep_f64<WV, UN, LY, true>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr,
+                               e.slice_len, e.idx, e.w, e.nslices, N_int, f, uo, un, dt, slot, remap);
         else
-            hipLaunchKernelGGL((k_sweep_f64<WV, UN, false>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr,
+            hipLaunchKernelGGL((k_sweep_f64<WV, UN, LY, false>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr,
                                e.slice_len, e.idx, e.w, e.nslices, N_int, f, uo, un, dt, slot, remap);
         return hipGetLastError();
     }
 };
 
-template <int WV, int UN>
+template <int WV, int UN, int LY>
 struct SweepF32 {
     static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const float *r, const float *eo, float *en,
                           float dt, int remap) {
-        hipLaunchKernelGGL((k_sweep_f32<WV, UN>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s, e.slice_ptr,
-                           e.slice_len, e.idx, e.w32, e.nslices, N_int, r, eo, en, dt, remap);
+        if (!e.nslices) return hipSuccess;
+        hipLaunchKernelGGL((k_sweep_f32<WV, UN, LY>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
+                           e.slice_ptr, e.slice_len, e.idx, e.w32, e.nslices, N_int, r, eo, en, dt, remap);
         return hipGetLastError();
     }
 };
 
-template <int WV, int UN>
+template <int WV, int UN, int LY>
 struct ApplyF64 {
     static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const double *u, double *Lu, const double *f,
                           unsigned long long *slot, int remap) {
-        hipLaunchKernelGGL((k_apply_f64<WV, UN>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s, e.slice_ptr,
-                           e.slice_len, e.idx, e.w, e.nslices, N_int, u, Lu, f, slot, remap);
+        if (!e.nslices) return hipSuccess;
+        hipLaunchKernelGGL((k_apply_f64<WV, UN, LY>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
+                           e.slice_ptr, e.slice_len, e.idx, e.w, e.nslices, N_int, u, Lu, f, slot, remap);
         return hipGetLastError();
     }
 };
 
-template <int WV, int UN>
+template <int WV, int UN, int LY>
 struct OuterRes {
     static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const double *f, const double *u, float *r32,
                           float *e0, unsigned long long *slot, int remap) {
-        hipLaunchKernelGGL((k_outer_residual<WV, UN>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
+        if (!e.nslices) return hipSuccess;
+        hipLaunchKernelGGL((k_outer_residual<WV, UN, LY>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
                            e.slice_ptr, e.slice_len, e.idx, e.w, e.nslices, N_int, f, u, r32, e0, slot, remap);
         return hipGetLastError();
     }
@@ -372,30 +441,32 @@ struct OuterRes {
 
 hipError_t launch_pack_ell(hipStream_t s, int64_t N_int, int32_t n_max, const int32_t *perm, const int32_t *iperm,
                            const int32_t *sten, const int16_t *nrow, const double *w_can, const Ell &e) {
-    const int64_t total = e.nslices * kSlice * (int64_t)n_max;
-    hipLaunchKernelGGL(k_pack_ell, dim3(grid1d(total, 256)), dim3(256), 0, s, N_int, n_max, e.nslices, perm, iperm,
-                       sten, nrow, w_can, e.slice_ptr, e.slice_len, e.idx, e.w, e.w32);
+    const int32_t kmax = e.max_len;
+    const int64_t total = e.nslices * kSlice * (int64_t)kmax;
+    if (!total) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_ell, dim3(grid1d(total, 256)), dim3(256), 0, s, N_int, n_max, kmax, e.nslices, e.layout,
+                       perm, iperm, sten, nrow, w_can, e.slice_ptr, e.slice_len, e.idx, e.w, e.w32);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
                             const double *u_old, double *u_new, double dt, unsigned long long *res_slot) {
-    return dispatch_shape<SweepF64>(c, s, e, N_int, f, u_old, u_new, dt, res_slot, c.xcd_remap);
+    return dispatch_shape<SweepF64>(c, e.layout, s, e, N_int, f, u_old, u_new, dt, res_slot, c.xcd_remap);
 }
 
 hipError_t launch_sweep_f32(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const float *r,
                             const float *e_old, float *e_new, float dt) {
-    return dispatch_shape<SweepF32>(c, s, e, N_int, r, e_old, e_new, dt, c.xcd_remap);
+    return dispatch_shape<SweepF32>(c, e.layout, s, e, N_int, r, e_old, e_new, dt, c.xcd_remap);
 }
 
 hipError_t launch_apply_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *u,
                             double *Lu, const double *f, unsigned long long *res_slot) {
-    return dispatch_shape<ApplyF64>(c, s, e, N_int, u, Lu, f, res_slot, c.xcd_remap);
+    return dispatch_shape<ApplyF64>(c, e.layout, s, e, N_int, u, Lu, f, res_slot, c.xcd_remap);
 }
 
 hipError_t launch_outer_residual(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
                                  const double *u, float *r32, float *e0, unsigned long long *res_slot) {
-    return dispatch_shape<OuterRes>(c, s, e, N_int, f, u, r32, e0, res_slot, c.xcd_remap);
+    return dispatch_shape<OuterRes>(c, e.layout, s, e, N_int, f, u, r32, e0, res_slot, c.xcd_remap);
 }
 
 hipError_t launch_add_correction(hipStream_t s, int64_t N_int, double *u, const float *e) {
@@ -415,8 +486,9 @@ hipError_t launch_sum_partials(hipStream_t s, const double *partials, int n, dou
 }
 
 hipError_t launch_transpose_scatter(hipStream_t s, const Ell &e, int64_t N_int, const double *v, double *out) {
+    if (!e.nslices) return hipSuccess;
     hipLaunchKernelGGL((k_transpose_scatter<4>), dim3(grid1d(e.nslices, 4)), dim3(256), 0, s, e.slice_ptr,
-                       e.slice_len, e.idx, e.w, e.nslices, N_int, v, out);
+                       e.slice_len, e.idx, e.w, e.nslices, N_int, v, out, e.layout);
     return hipGetLastError();
 }
 

@@ -533,6 +533,9 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
         for (int64_t k = 0; k < N; ++k) iperm[perm[k]] = (int32_t)k;
     }
     Ell e;
+    // packed layout: entry pairs as vectors unless RBF_ELL_LAYOUT=0
+    const char *lay = std::getenv("RBF_ELL_LAYOUT");
+    e.layout = (lay && lay[0] == '0') ? 0 : 1;
     e.nslices = (N_int + kSlice - 1) / kSlice;
     std::vector<int64_t> sptr((size_t)e.nslices + 1);
     std::vector<int32_t> slen((size_t)e.nslices);
@@ -542,6 +545,7 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
         int32_t len = 0;
         for (int64_t i = s * kSlice; i < std::min<int64_t>(N_int, (s + 1) * kSlice); ++i)
             len = std::max<int32_t>(len, h->nrow_h[perm[i]]);
+        if (e.layout == 1) len += len & 1;
         slen[s] = len;
         sptr[s] = acc;
         acc += (int64_t)len * kSlice;
@@ -580,7 +584,7 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
     h->have_w32 = keep_fp32 != 0;
     // a tuned shape for this operator, if cached
     char key[160];
-    std::snprintf(key, sizeof key, "sweep|%s|%" PRId64 "|%" PRId64 "|%d", h->arch, N_int, e.elems, e.max_len);
+    std::snprintf(key, sizeof key, "sweep|%s|L%d|%" PRId64 "|%" PRId64 "|%d", h->arch, e.layout, N_int, e.elems, e.max_len);
     int v[3];
     if (cache_lookup(key, v, 3)) {
         h->cfg.waves_per_block = v[0];
@@ -1190,7 +1194,7 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
             }
     h->cfg = bestc;
     char key[160];
-    std::snprintf(key, sizeof key, "sweep|%s|%" PRId64 "|%" PRId64 "|%d", h->arch, Ni, h->ell.elems, h->ell.max_len);
+    std::snprintf(key, sizeof key, "sweep|%s|L%d|%" PRId64 "|%" PRId64 "|%d", h->arch, h->ell.layout, Ni, h->ell.elems, h->ell.max_len);
     int v[3] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap};
     cache_store(key, v, 3);
     return RBF_OK;

@@ -43,6 +43,7 @@ struct SweepCfg {
 // k < slice_len[s].  Within a row, entries are sorted by internal column id
 // so that the k-th gathers of neighbouring rows hit neighbouring addresses.
 struct Ell {
+    int layout = 1;                // 0: one element per lane per entry; 1: entry pairs as vectors (k_sweep.hip)
     int64_t nslices = 0;
     int64_t elems = 0;
     int32_t max_len = 0;
