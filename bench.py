@@ -149,6 +149,177 @@ def cpu_baseline(budget_s=10.0):
                       f"({nint} interior rows, m=4, n=70), {budget_s:.0f} s window after an untimed oracle setup"}
 
 
+def _progress(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _dev(a):
+    import torch
+    return torch.tensor(a, dtype=torch.float64, device="cuda")
+
+
+def run_cube8m(mode_name, target, piece_steps=40000, max_steps=3_000_000):
+    """Time to L-inf error `target` against the exact solution on the 8M-node
+    cube (m = 4, n = 70), FP64 or FP32 inner sweeps with FP64 refinement; the
+    error is checked every 500 steps in both modes.  Runs in pieces of
+    `piece_steps` steps (the state is just u) so progress is printed."""
+    import torch
+
+    import rbf_inputs as ri
+    from paper_2502_12878_amd import RBF_MODE_FP64, RBF_MODE_MIXED, Problem
+    mode = RBF_MODE_MIXED if mode_name == "fp32_refine" else RBF_MODE_FP64
+    wl = ri.workload("cube8M")
+    p = Problem(0)
+    t0 = time.perf_counter()
+    xyz, typ = p.build_nodes(wl.dim, wl.side, wl.jitter, wl.seed)
+    p.set_nodes(xyz, typ)
+    del xyz, typ
+    p.build_stencils(wl.n)
+    p.compute_weights(wl.m, keep_fp32=(mode == RBF_MODE_MIXED))
+    p.autotune()
+    setup_s = time.perf_counter() - t0
+    xyz_h, typ_h = wl.nodes()
+    u_ex, f, g, u0 = ri.manufactured(wl.dim, xyz_h, typ_h)
+    nint = int((typ_h == 0).sum())
+    del xyz_h
+    fd, uref, u = _dev(f), _dev(u_ex), _dev(u0)
+    steps = 0
+    dev_s = 0.0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    rep = None
+    while steps < max_steps:
+        st, rep = p.iterate(fd, u, wl.dt, piece_steps, 0.0, 500, mode=mode, inner_steps=500, u_ref=uref,
+                            err_target=target)
+        steps += rep["steps"]
+        dev_s += rep["seconds"]
+        _progress(f"cube8M {mode_name}: {steps} steps, err_inf {rep['err_inf']:.3e}, device {dev_s:.1f} s")
+        if st != 0 or rep["err_met"]:
+            break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    sample = u[:: 1009].cpu().numpy()
+    return {"workload": "cube8M: 3D 200^3 jittered grid (seed 2), m=4, n=70, dt=0.15*h^2/6", "mode": mode_name,
+            "target_err_inf": target, "reached": bool(rep["err_met"]), "steps": steps, "wall_s": round(wall, 2),
+            "device_s": round(dev_s, 2), "ms_per_step": 1e3 * dev_s / max(1, steps), "err_inf": rep["err_inf"],
+            "err_mean_abs": rep["err_mean_abs"], "interior_nodes": nint, "setup_s": round(setup_s, 2),
+            "alg_bytes_per_update": 12 * wl.n + 24 if mode == RBF_MODE_FP64 else 8 * wl.n + 12,
+            "u_sample_every_1009": {"sum": float(sample.sum()), "sumsq": float((sample ** 2).sum())}}
+
+
+def run_cube4m_bands(steps=1000):
+    """Per-node orders by distance to the boundary (m = 2 / 4 / 6, n = 20 / 70 /
+    168) on the 159^3 cube: supports with per-node sizes, every weight system in
+    one persistent launch, then FP64 sweeps on the sliced operator."""
+    import numpy as np
+    import torch
+
+    import rbf_inputs as ri
+    from paper_2502_12878_amd import Problem
+    wl = ri.workload("cube4M_bands")
+    xyz_h, typ_h = wl.nodes()
+    m, n = ri.order_bands(3, xyz_h, typ_h, wl.h)
+    interior = typ_h == 0
+    classes = {}
+    flops = 0.0
+    alg_bytes = 0
+    for mm in (2, 4, 6):
+        sel = interior & (m == mm)
+        cnt = int(sel.sum())
+        nn = 2 * ri.num_monomials(3, mm)
+        S = nn + ri.num_monomials(3, mm)
+        # elimination (separate multiply and subtract per update) plus back substitution
+        f_sys = sum(2.0 * (S - k - 1) * (S - k) for k in range(S)) + 2.0 * S * S
+        classes[str(mm)] = {"rows": cnt, "n": nn, "S": S}
+        flops += cnt * f_sys
+        alg_bytes += cnt * (12 * nn + 24)
+    p = Problem(0)
+    xd, td = p.build_nodes(3, wl.side, wl.jitter, wl.seed)
+    p.set_nodes(xd, td)
+    del xd, td
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.build_stencils(n_per_node=n)
+    t1 = time.perf_counter()
+    p.compute_weights(m_per_node=m)
+    t2 = time.perf_counter()
+    p.autotune()
+    u_ex, f, g, u0 = ri.manufactured(3, xyz_h, typ_h)
+    s = {"p": p, "wl": wl, "f": _dev(f), "u0": _dev(u0)}
+    wall, per_sweep, nsw, rep = time_sweeps(s, steps, 100)
+    nint = int(interior.sum())
+    return {"workload": "cube4M_bands: 3D 159^3 jittered grid (seed 3), m=2/4/6 by distance to the boundary "
+                        "(<3h, <6h, else), n=2M", "classes": classes, "interior_nodes": nint,
+            "stencils_s": round(t1 - t0, 3), "weights_s": round(t2 - t1, 3),
+            "weights_gflops": round(flops / (t2 - t1) / 1e9, 1), "weights_flop_total": flops,
+            "sweep_kernel_ms": round(1e3 * per_sweep, 4), "node_updates_per_s": nint / per_sweep,
+            "sweep_alg_GBps": round(alg_bytes / per_sweep / 1e9, 1),
+            "sweep_hbm_frac": round(alg_bytes / per_sweep / 1e9 / PEAK_HBM_GBS, 4), "res_final": rep["res_final"]}
+
+
+def run_cube2m_adjoint(directions=32):
+    """dJ/df for J = 1/2 |u_K - u_target|^2 (interior) after K = 2000 steps on
+    the 126^3 cube (m = 4), by checkpointed forward + transposed sweeps, against
+    central differences on `directions` seeded smooth directions."""
+    import numpy as np
+    import torch
+
+    import rbf_inputs as ri
+    from paper_2502_12878_amd import Problem, SolveK
+    wl = ri.workload("cube2M_adjoint")
+    K, every = wl.extra["K"], wl.extra["every"]
+    p = Problem(0)
+    xd, td = p.build_nodes(3, wl.side, wl.jitter, wl.seed)
+    p.set_nodes(xd, td)
+    del xd, td
+    p.build_stencils(wl.n)
+    p.compute_weights(wl.m)
+    p.autotune()
+    xyz_h, typ_h = wl.nodes()
+    I = typ_h == 0
+    It = torch.tensor(I, device="cuda")
+    f = _dev(np.where(I, ri.gaussian_field(3, xyz_h, wl.seed + 100), 0.0))
+    f_t = f + 0.1 * _dev(np.where(I, ri.gaussian_field(3, xyz_h, wl.seed + 200), 0.0))
+    zero = torch.zeros_like(f)
+    with torch.no_grad():
+        u_t = SolveK.apply(f_t, p, zero, K, every, wl.dt)
+
+    def J(ff):
+        d = (SolveK.apply(ff, p, zero, K, every, wl.dt) - u_t)[It]
+        return 0.5 * (d * d).sum()
+
+    fr = f.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = J(fr)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    grad = fr.grad.detach()
+    eps = 1e-2 * f.abs().max().item()
+    gnorm = grad.norm().item()
+    errs = []
+    with torch.no_grad():
+        j = 0
+        seed_off = 0
+        while len(errs) < directions:
+            v = _dev(np.where(I, ri.gaussian_field(3, xyz_h, wl.seed + 300 + j + seed_off), 0.0))
+            v = v / v.abs().max()
+            fd = ((J(f + eps * v) - J(f - eps * v)) / (2 * eps)).item()
+            if abs(fd) < 1e-3 * gnorm * v.norm().item():
+                seed_off += 1000  # deterministic redraw of a direction nearly orthogonal to the gradient
+                continue
+            errs.append(abs((grad * v).sum().item() - fd) / abs(fd))
+            _progress(f"direction {j}: rel err {errs[-1]:.2e}")
+            j += 1
+    return {"workload": "cube2M_adjoint: 3D 126^3 jittered grid (seed 4), m=4, n=70, K=2000, checkpoints every 100",
+            "interior_nodes": int(I.sum()), "forward_ckpt_s": round(t1 - t0, 3), "adjoint_s": round(t2 - t1, 3),
+            "J": loss.item(), "fd_eps": eps, "directions": directions, "max_rel_err_vs_fd": max(errs),
+            "median_rel_err_vs_fd": float(np.median(errs)), "rel_errs": errs}
+
+
 def stream_ceiling(nbytes=1 << 30, reps=20):
     """Achievable HBM rates on this device for context: a 1 GiB device copy
     (read + write) and a 1 GiB read-only sum, timed with events."""
@@ -194,6 +365,10 @@ def main():
     ap.add_argument("--no-tte", action="store_true", help="skip the time-to-error comparison")
     ap.add_argument("--tte-target", type=float, default=1e-6)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--workload", default="cube1M",
+                    choices=["cube1M", "cube8M", "cube4M_bands", "cube2M_adjoint"],
+                    help="cube1M: the benchmark line; the others print their own measurement line")
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32_refine"], help="cube8M: iteration mode")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -204,6 +379,16 @@ def main():
     import torch
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.workload != "cube1M":
+        if args.workload == "cube8M":
+            out = run_cube8m(args.mode, args.tte_target)
+        elif args.workload == "cube4M_bands":
+            out = run_cube4m_bands()
+        else:
+            out = run_cube2m_adjoint()
+        out["device"] = torch.cuda.get_device_name(0)
+        print(json.dumps(out))
         return
     orders = [int(x) for x in args.orders.split(",") if x]
     per_order = {}

@@ -190,8 +190,10 @@ rbf_status rbf_apply(rbf_handle *h, const double *u_dev, double *Lu_dev);
 
 /* out_dev[c] = sum over interior rows r and support entries k with
  * idx_rk = c of w_rk v_dev[r], for interior c; 0 on Dirichlet nodes (nothing
- * flows into Dirichlet columns).  Uses FP64 atomics: the summation order, and
- * so the last bits, may vary between calls. */
+ * flows into Dirichlet columns).  The first transposed call builds L_II^T once
+ * (entries of each column sorted by row), so results are deterministic; with
+ * the environment variable RBF_TRANSPOSE_SCATTER=1 a scatter with FP64 atomics
+ * is used instead (last bits may then vary between calls). */
 rbf_status rbf_apply_transpose(rbf_handle *h, const double *v_dev, double *out_dev);
 
 /* Max-norm residual max|L u - f| over interior nodes, written to *res_host.
@@ -211,8 +213,10 @@ rbf_status rbf_forward_ckpt(rbf_handle *h, const double *f_dev, const double *u0
  * G = I + dt L_II and gK = dJ/du_K, grad = -dt sum_{j=0}^{K-1} (G^T)^j gK on
  * interior nodes, 0 on Dirichlet nodes.  The transposed steps run segment by
  * segment in reverse over the `every`-step checkpoint segments; ckpt_dev may
- * be NULL because this gradient does not depend on the states.  Transposes
- * use FP64 atomics (last-bit nondeterminism). */
+ * be NULL because this gradient does not depend on the states.  Each
+ * transposed step is a gather sweep over L_II^T (built once, deterministic;
+ * RBF_TRANSPOSE_SCATTER=1 selects the atomic scatter as for
+ * rbf_apply_transpose). */
 rbf_status rbf_adjoint_f(rbf_handle *h, const double *gK_dev, int64_t K, int64_t every,
                          const double *ckpt_dev, double *grad_f_dev, double dt);
 

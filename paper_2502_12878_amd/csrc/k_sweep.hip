@@ -152,6 +152,65 @@ struct RowDot<T, U, 1> {
     }
 };
 
+// Layout 1, software-pipelined: the index and weight vectors of the next
+// group of U entries are requested before the current group's gathers, so a
+// wavefront keeps two groups of stream loads in flight.
+template <typename T, int U>
+struct RowDot<T, U, 2> {
+    __device__ static __forceinline__ T run(const int32_t *__restrict__ idx, const T *__restrict__ w,
+                                            const T *__restrict__ x, int64_t base, int lane, int len) {
+        typedef typename Vec2<T>::type V;
+        constexpr int P = U / 2;
+        T acc = T(0);
+        const i32x2 *ip = (const i32x2 *)(idx + base) + lane;
+        const V *wp = (const V *)(w + base) + lane;
+        const int groups = len / U;
+        i32x2 jn[P];
+        V wn[P];
+        if (groups > 0) {
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                jn[q] = __builtin_nontemporal_load(ip + q * kSlice);
+                wn[q] = __builtin_nontemporal_load(wp + q * kSlice);
+            }
+        }
+        for (int g = 0; g < groups; ++g) {
+            i32x2 jc[P];
+            V wc[P];
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                jc[q] = jn[q];
+                wc[q] = wn[q];
+            }
+            if (g + 1 < groups) {
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    jn[q] = __builtin_nontemporal_load(ip + ((g + 1) * P + q) * kSlice);
+                    wn[q] = __builtin_nontemporal_load(wp + ((g + 1) * P + q) * kSlice);
+                }
+            }
+            T xx[U];
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                xx[2 * q] = x[jc[q].x];
+                xx[2 * q + 1] = x[jc[q].y];
+            }
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                acc = fma(wc[q].x, xx[2 * q], acc);
+                acc = fma(wc[q].y, xx[2 * q + 1], acc);
+            }
+        }
+        for (int k = groups * U; k < len; k += 2) {
+            const i32x2 j = __builtin_nontemporal_load(ip + (k >> 1) * kSlice);
+            const V ww = __builtin_nontemporal_load(wp + (k >> 1) * kSlice);
+            acc = fma(ww.x, x[j.x], acc);
+            acc = fma(ww.y, x[j.y], acc);
+        }
+        return acc;
+    }
+};
+
 // One explicit step on every interior row; optionally max |rho| into slot.
 template <int WAVES, int U, int LAYOUT, bool REDUCE>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
@@ -160,7 +219,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
     const double *__restrict__ u_old, double *__restrict__ u_new, double dt, unsigned long long *res_slot,
     int remap) {
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
-    const int64_t slice = blk * WAVES + (threadIdx.x >> 6);
+    const int64_t slice = blk * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     unsigned long long bits = 0;
     if (slice < nslices) {
@@ -183,7 +242,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f32(
     const float *__restrict__ w, int64_t nslices, int64_t N_int, const float *__restrict__ r,
     const float *__restrict__ e_old, float *__restrict__ e_new, float dt, int remap) {
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
-    const int64_t slice = blk * WAVES + (threadIdx.x >> 6);
+    const int64_t slice = blk * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (slice >= nslices) return;
     const int len = slice_len[slice];
@@ -199,7 +258,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_apply_f64(
     const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ u,
     double *__restrict__ Lu, const double *__restrict__ f, unsigned long long *res_slot, int remap) {
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
-    const int64_t slice = blk * WAVES + (threadIdx.x >> 6);
+    const int64_t slice = blk * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     unsigned long long bits = 0;
     if (slice < nslices) {
@@ -223,7 +282,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_outer_residual(
     const double *__restrict__ u, float *__restrict__ r32, float *__restrict__ e0, unsigned long long *res_slot,
     int remap) {
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
-    const int64_t slice = blk * WAVES + (threadIdx.x >> 6);
+    const int64_t slice = blk * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     unsigned long long bits = 0;
     if (slice < nslices) {
@@ -238,6 +297,27 @@ __global__ __launch_bounds__(WAVES * 64) void k_outer_residual(
         }
     }
     if (res_slot) block_max_to_slot<WAVES>(bits, res_slot);
+}
+
+// One adjoint step on the transposed operator (rows of L^T = interior columns
+// of L): lam_new = lam + dt (L_II^T lam), acc += lam_new.
+template <int WAVES, int U, int LAYOUT>
+__global__ __launch_bounds__(WAVES * 64) void k_adjoint_gather(
+    const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
+    const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ lam_old,
+    double *__restrict__ lam_new, double *__restrict__ acc, double dt, int remap) {
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
+    const int64_t slice = blk * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (slice >= nslices) return;
+    const int len = slice_len[slice];
+    const double s = RowDot<double, U, LAYOUT>::run(idx, w, lam_old, slice_ptr[slice], lane, len);
+    const int64_t row = slice * kSlice + lane;
+    if (row < N_int) {
+        const double l = lam_old[row] + dt * s;
+        lam_new[row] = l;
+        acc[row] += l;
+    }
 }
 
 // Transpose scatter: out[c] += w_rc v_r for interior rows r and interior c.
@@ -377,9 +457,10 @@ inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs)
 // Dispatch over the tuned (waves per block, unroll, layout) triples.
 template <template <int, int, int> class F, typename... A>
 hipError_t dispatch_shape(const SweepCfg &c, int layout, A &&...a) {
-#define RBF_CASE(WV, UN)                                                  \
-    if (c.waves_per_block == WV && c.unroll == UN) {                      \
-        return layout ? F<WV, UN, 1>::run(a...) : F<WV, UN, 0>::run(a...); \
+#define RBF_CASE(WV, UN)                                                                            \
+    if (c.waves_per_block == WV && c.unroll == UN) {                                                \
+        if (!layout) return F<WV, UN, 0>::run(a...);                                                \
+        return c.pipeline ? F<WV, UN, 2>::run(a...) : F<WV, UN, 1>::run(a...);                       \
     }
     RBF_CASE(2, 4) RBF_CASE(2, 8) RBF_CASE(2, 16)
     RBF_CASE(4, 4) RBF_CASE(4, 8) RBF_CASE(4, 16)
@@ -427,6 +508,17 @@ struct ApplyF64 {
 };
 
 template <int WV, int UN, int LY>
+struct AdjGather {
+    static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const double *lo, double *ln, double *acc,
+                          double dt, int remap) {
+        if (!e.nslices) return hipSuccess;
+        hipLaunchKernelGGL((k_adjoint_gather<WV, UN, LY>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
+                           e.slice_ptr, e.slice_len, e.idx, e.w, e.nslices, N_int, lo, ln, acc, dt, remap);
+        return hipGetLastError();
+    }
+};
+
+template <int WV, int UN, int LY>
 struct OuterRes {
     static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const double *f, const double *u, float *r32,
                           float *e0, unsigned long long *slot, int remap) {
@@ -467,6 +559,11 @@ hipError_t launch_apply_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int6
 hipError_t launch_outer_residual(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
                                  const double *u, float *r32, float *e0, unsigned long long *res_slot) {
     return dispatch_shape<OuterRes>(c, e.layout, s, e, N_int, f, u, r32, e0, res_slot, c.xcd_remap);
+}
+
+hipError_t launch_adjoint_gather(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *lam_old,
+                                 double *lam_new, double *acc, double dt) {
+    return dispatch_shape<AdjGather>(c, e.layout, s, e, N_int, lam_old, lam_new, acc, dt, c.xcd_remap);
 }
 
 hipError_t launch_add_correction(hipStream_t s, int64_t N_int, double *u, const float *e) {

@@ -566,13 +566,15 @@ hipError_t launch_weights_items(hipStream_t s, int dim, int64_t N, const double 
                                 const int16_t *nrow, int32_t n_max, const int32_t *rows, const int8_t *mrow,
                                 double *w_out, double *scratch, int64_t slab, int panel, DevStatus *status,
                                 const void *items, int64_t nitems, int32_t *counter, int S_small, int S_mid,
-                                int S_large, int grid, size_t *lds_used) {
+                                int S_large, int grid, int nslabs, size_t *lds_used) {
     WCtx cx{dim, N, xyz, sten, nrow, n_max, rows, mrow, w_out, scratch, slab, panel, status};
     const size_t lds = lds_total(S_small, S_mid, S_large, panel);
     if (lds_used) *lds_used = lds;
+    if (grid <= 0) return hipErrorInvalidConfiguration;
+    // a LARGE item uses scratch slab blockIdx.x: never launch more groups than slabs
+    if (S_large > 0 && (scratch == nullptr || grid > nslabs)) return hipErrorInvalidConfiguration;
     hipError_t e = hipFuncSetAttribute((const void *)k_weights, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    if (grid <= 0) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_weights, dim3(grid), dim3(kBS), lds, s, cx, (const Item *)items, nitems, counter, S_small,
                        S_mid);
     return hipGetLastError();

@@ -110,6 +110,11 @@ void drop_operator(rbf_handle *h) {
     free_t(h, h->ell.w);
     free_t(h, h->ell.w32);
     h->ell = Ell{};
+    free_t(h, h->ellT.slice_ptr);
+    free_t(h, h->ellT.slice_len);
+    free_t(h, h->ellT.idx);
+    free_t(h, h->ellT.w);
+    h->ellT = Ell{};
     free_t(h, h->ua);
     free_t(h, h->ub);
     free_t(h, h->fint);
@@ -585,11 +590,20 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
     // a tuned shape for this operator, if cached
     char key[160];
     std::snprintf(key, sizeof key, "sweep|%s|L%d|%" PRId64 "|%" PRId64 "|%d", h->arch, e.layout, N_int, e.elems, e.max_len);
-    int v[3];
-    if (cache_lookup(key, v, 3)) {
+    int v[4];
+    if (cache_lookup(key, v, 4)) {
         h->cfg.waves_per_block = v[0];
         h->cfg.unroll = v[1];
         h->cfg.xcd_remap = v[2];
+        h->cfg.pipeline = e.layout ? v[3] : 0;
+    }
+    std::snprintf(key, sizeof key, "sweep32|%s|L%d|%" PRId64 "|%" PRId64 "|%d", h->arch, e.layout, N_int, e.elems,
+                  e.max_len);
+    if (cache_lookup(key, v, 4)) {
+        h->cfg32.waves_per_block = v[0];
+        h->cfg32.unroll = v[1];
+        h->cfg32.xcd_remap = v[2];
+        h->cfg32.pipeline = e.layout ? v[3] : 0;
     }
     return RBF_OK;
 }
@@ -662,8 +676,15 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
         HIPCHK(h, hipMemcpyAsync(d_items, items.data(), items.size(), hipMemcpyHostToDevice, h->stream));
         const int64_t slab = S_large > 0 ? (int64_t)S_large * (S_large + 1) + 32 : 0;
         const int cand[3] = {8, 16, 32};
+        // Every LARGE workgroup indexes its own scratch slab by blockIdx, so the
+        // slab count must cover the largest grid launched below: the full
+        // launch (all item kinds) and the panel-timing launches (LARGE items
+        // only, smaller LDS footprint, hence possibly more resident groups).
         int grid_max = 0;
-        for (int pc : cand) grid_max = std::max(grid_max, weights_grid(S_small, S_mid, S_large, pc));
+        for (int pc : cand) {
+            grid_max = std::max(grid_max, weights_grid(S_small, S_mid, S_large, pc));
+            if (S_large > 0) grid_max = std::max(grid_max, weights_grid(0, 0, S_large, pc));
+        }
         if (grid_max <= 0) return fail(h, RBF_EHIP, "weight solver does not fit on the device");
         if (S_large > 0) ALLOC(h, scratch, double, (size_t)slab * grid_max);
         // panel width: cached choice, else time the candidates on a sample
@@ -682,7 +703,8 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
                     HIPCHK(h, hipEventRecord(h->ev0, h->stream));
                     HIPCHK(h, launch_weights_items(h->stream, dim, N, h->xyz, h->sten, h->nrow, h->n_max, d_rows, d_m,
                                                    h->w_can, scratch, slab, pc, h->dstatus, d_items, sample, counter,
-                                                   0, 0, S_large, weights_grid(0, 0, S_large, pc), nullptr));
+                                                   0, 0, S_large, weights_grid(0, 0, S_large, pc), grid_max,
+                                                   nullptr));
                     HIPCHK(h, hipEventRecord(h->ev1, h->stream));
                     HIPCHK(h, hipEventSynchronize(h->ev1));
                     float ms = 0.f;
@@ -702,7 +724,7 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
         HIPCHK(h, hipMemsetAsync(counter, 0, sizeof(int32_t), h->stream));
         HIPCHK(h, launch_weights_items(h->stream, dim, N, h->xyz, h->sten, h->nrow, h->n_max, d_rows, d_m, h->w_can,
                                        scratch, slab, panel, h->dstatus, d_items, nitems, counter, S_small, S_mid,
-                                       S_large, weights_grid(S_small, S_mid, S_large, panel), nullptr));
+                                       S_large, weights_grid(S_small, S_mid, S_large, panel), grid_max, nullptr));
         DevStatus ds;
         st = read_status(h, &ds);
         dfree(h, d_rows);
@@ -806,6 +828,72 @@ extern "C" rbf_status rbf_apply(rbf_handle *h, const double *u_dev, double *Lu_d
     return RBF_OK;
 }
 
+// The transposed interior operator in the sliced layout (built once per
+// operator): column c of L_II becomes row c of L_II^T, its entries sorted by
+// row so that the gather sums in a fixed order.
+static rbf_status build_transpose(rbf_handle *h) {
+    if (h->ellT.idx || !h->N_int) return RBF_OK;
+    const int64_t N = h->N, Ni = h->N_int;
+    int32_t *cnt = nullptr, *cursor = nullptr, *rows_t = nullptr;
+    int64_t *start = nullptr;
+    double *w_t = nullptr;
+    ALLOC(h, cnt, int32_t, Ni);
+    HIPCHK(h, hipMemsetAsync(cnt, 0, sizeof(int32_t) * Ni, h->stream));
+    HIPCHK(h, launch_tcount(h->stream, N, h->n_max, Ni, h->type, h->iperm, h->sten, h->nrow, cnt));
+    std::vector<int32_t> ch((size_t)Ni);
+    HIPCHK(h, hipMemcpyAsync(ch.data(), cnt, sizeof(int32_t) * Ni, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    std::vector<int64_t> st((size_t)Ni + 1);
+    st[0] = 0;
+    for (int64_t c = 0; c < Ni; ++c) st[c + 1] = st[c] + ch[c];
+    const int64_t nnz = st[Ni];
+    Ell e;
+    e.layout = 1;
+    e.nslices = (Ni + kSlice - 1) / kSlice;
+    std::vector<int64_t> sptr((size_t)e.nslices + 1);
+    std::vector<int32_t> slen((size_t)e.nslices);
+    int64_t acc = 0;
+    for (int64_t s = 0; s < e.nslices; ++s) {
+        int32_t len = 0;
+        for (int64_t c = s * kSlice; c < std::min<int64_t>(Ni, (s + 1) * kSlice); ++c) len = std::max(len, ch[c]);
+        len += len & 1;
+        slen[s] = len;
+        sptr[s] = acc;
+        acc += (int64_t)len * kSlice;
+        e.max_len = std::max(e.max_len, len);
+    }
+    sptr[e.nslices] = acc;
+    e.elems = acc;
+    ALLOC(h, start, int64_t, Ni + 1);
+    ALLOC(h, cursor, int32_t, Ni);
+    ALLOC(h, rows_t, int32_t, std::max<int64_t>(1, nnz));
+    ALLOC(h, w_t, double, std::max<int64_t>(1, nnz));
+    ALLOC(h, e.slice_ptr, int64_t, e.nslices + 1);
+    ALLOC(h, e.slice_len, int32_t, e.nslices);
+    ALLOC(h, e.idx, int32_t, std::max<int64_t>(1, e.elems));
+    ALLOC(h, e.w, double, std::max<int64_t>(1, e.elems));
+    HIPCHK(h, hipMemcpyAsync(start, st.data(), sizeof(int64_t) * (Ni + 1), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(e.slice_ptr, sptr.data(), sizeof(int64_t) * (e.nslices + 1), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(e.slice_len, slen.data(), sizeof(int32_t) * e.nslices, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemsetAsync(cursor, 0, sizeof(int32_t) * Ni, h->stream));
+    HIPCHK(h, launch_tfill(h->stream, N, h->n_max, Ni, h->type, h->iperm, h->sten, h->nrow, h->w_can, start, cursor,
+                           rows_t, w_t));
+    HIPCHK(h, launch_tpack(h->stream, Ni, start, rows_t, w_t, e));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    dfree(h, cnt);
+    dfree(h, cursor);
+    dfree(h, start);
+    dfree(h, rows_t);
+    dfree(h, w_t);
+    h->ellT = e;
+    return RBF_OK;
+}
+
+static bool use_scatter_transpose() {
+    const char *v = std::getenv("RBF_TRANSPOSE_SCATTER");
+    return v && v[0] == '1';
+}
+
 extern "C" rbf_status rbf_apply_transpose(rbf_handle *h, const double *v_dev, double *out_dev) {
     if (!h) return RBF_EINVAL;
     h->err.clear();
@@ -815,7 +903,13 @@ extern "C" rbf_status rbf_apply_transpose(rbf_handle *h, const double *v_dev, do
     const int64_t N = h->N, Ni = h->N_int;
     HIPCHK(h, launch_gather(h->stream, N, h->perm, v_dev, h->ua));
     HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->tmp));
-    if (Ni) HIPCHK(h, launch_transpose_scatter(h->stream, h->ell, Ni, h->ua, h->tmp));
+    if (Ni && use_scatter_transpose()) {
+        HIPCHK(h, launch_transpose_scatter(h->stream, h->ell, Ni, h->ua, h->tmp));
+    } else if (Ni) {
+        rbf_status st = build_transpose(h);
+        if (st) return st;
+        HIPCHK(h, launch_apply_f64(h->stream, h->cfg, h->ellT, Ni, h->ua, h->tmp, nullptr, nullptr));
+    }
     HIPCHK(h, launch_scatter(h->stream, N, h->perm, h->tmp, out_dev));
     return RBF_OK;
 }
@@ -842,7 +936,7 @@ extern "C" rbf_status rbf_residual(rbf_handle *h, const double *f_dev, const dou
 }
 
 // ====================================================================== graphs
-enum GraphKind { kGraphF64 = 0, kGraphMixed = 1, kGraphAdjoint = 2, kGraphF64Quiet = 3 };
+enum GraphKind { kGraphF64 = 0, kGraphMixed = 1, kGraphAdjoint = 2, kGraphF64Quiet = 3, kGraphAdjointGather = 4 };
 
 // FP64 chunk: reset the residual slot, `steps` sweeps alternating ua/ub
 // (starting from ua when start == 0), the last one reporting max |rho|.
@@ -874,18 +968,26 @@ static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, d
         float *a = h->ea, *b = h->eb;
         const float dt32 = (float)dt;
         for (int i = 0; i < inner && e == hipSuccess; ++i) {
-            e = launch_sweep_f32(s, h->cfg, h->ell, Ni, h->r32, a, b, dt32);
+            e = launch_sweep_f32(s, h->cfg32, h->ell, Ni, h->r32, a, b, dt32);
             std::swap(a, b);
         }
         if (e == hipSuccess) e = launch_add_correction(s, Ni, h->ua, a);
         if (e == hipSuccess && steps)  // steps != 0: the reference is set
             e = launch_err_norm(s, h->N, h->ua, h->uref, h->part, kErrBlocks, h->dslots + 1);
     } else if (kind == kGraphAdjoint) {
-        // `steps` transposed steps: tmp += L^T lam (scatter), lam += dt tmp,
-        // acc += lam, tmp = 0.  ua = lam, ub = acc.
+        // `steps` transposed steps by scattering: tmp += L^T lam (FP64
+        // atomics), lam += dt tmp, acc += lam, tmp = 0.  ua = lam, ub = acc.
         for (int64_t i = 0; i < steps && e == hipSuccess; ++i) {
             e = launch_transpose_scatter(s, h->ell, Ni, h->ua, h->tmp);
             if (e == hipSuccess) e = launch_adjoint_update(s, Ni, dt, h->ua, h->ub, h->tmp);
+        }
+    } else if (kind == kGraphAdjointGather) {
+        // `steps` transposed steps by gathering on L^T: lam alternates between
+        // ua and ub (from `start`), acc = tmp accumulates every new lam.
+        double *a = start ? h->ub : h->ua, *b = start ? h->ua : h->ub;
+        for (int64_t i = 0; i < steps && e == hipSuccess; ++i) {
+            e = launch_adjoint_gather(s, h->cfg, h->ellT, Ni, a, b, h->tmp, dt);
+            std::swap(a, b);
         }
     }
     hipGraph_t graph = nullptr;
@@ -1134,30 +1236,46 @@ extern "C" rbf_status rbf_adjoint_f(rbf_handle *h, const double *gK_dev, int64_t
     if (!std::isfinite(dt)) return fail(h, RBF_EINVAL, "dt must be finite");
     DeviceGuard g(h->device);
     const int64_t N = h->N, Ni = h->N_int;
-    // lam (ua) = gK on interior rows; acc (ub) = lam; tmp = 0
+    const bool scatter = use_scatter_transpose();
+    if (!scatter) {
+        rbf_status st = build_transpose(h);
+        if (st) return st;
+    }
+    // lam = gK on interior rows (0 elsewhere); acc = lam
     HIPCHK(h, launch_gather(h->stream, N, h->perm, gK_dev, h->ua));
     HIPCHK(h, launch_fill_f64(h->stream, N - Ni, 0.0, h->ua + Ni));
-    HIPCHK(h, hipMemcpyAsync(h->ub, h->ua, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
-    HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->tmp));
+    if (scatter) {  // acc in ub, scatter target tmp
+        HIPCHK(h, hipMemcpyAsync(h->ub, h->ua, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->tmp));
+    } else {  // lam alternates ua/ub, acc in tmp
+        HIPCHK(h, hipMemcpyAsync(h->tmp, h->ua, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, launch_fill_f64(h->stream, N - Ni, 0.0, h->ub + Ni));
+    }
     // K-1 transposed steps, segment by segment from the last checkpoint
     // interval back to the first; the first interval has one step fewer.
     const int64_t nseg = K / every;
+    int cur = 0;
     for (int64_t seg = nseg - 1; seg >= 0; --seg) {
         const int64_t steps = seg == 0 ? every - 1 : every;
         if (steps <= 0) continue;
         hipGraphExec_t ex;
-        rbf_status st = get_graph(h, kGraphAdjoint, steps, 0, dt, 0, &ex);
+        rbf_status st = get_graph(h, scatter ? kGraphAdjoint : kGraphAdjointGather, steps, scatter ? 0 : cur, dt, 0, &ex);
         if (st) return st;
         HIPCHK(h, hipGraphLaunch(ex, h->stream));
+        if (!scatter && (steps & 1)) cur ^= 1;
     }
-    HIPCHK(h, launch_scale_interior(h->stream, N, Ni, -dt, h->ub, h->tmp));
-    HIPCHK(h, launch_scatter(h->stream, N, h->perm, h->tmp, grad_f_dev));
-    // leave tmp zeroed for the next transposed call
+    double *acc = scatter ? h->ub : h->tmp;
+    double *out = scatter ? h->tmp : h->ub;
+    HIPCHK(h, launch_scale_interior(h->stream, N, Ni, -dt, acc, out));
+    HIPCHK(h, launch_scatter(h->stream, N, h->perm, out, grad_f_dev));
+    // leave tmp zeroed for the next scattered transpose
     HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->tmp));
     return RBF_OK;
 }
 
 // ====================================================================== autotune
+// Time every candidate shape of the FP64 sweep (and of the FP32 sweep when an
+// FP32 copy exists) on the real operator and keep the fastest of each.
 extern "C" rbf_status rbf_autotune(rbf_handle *h) {
     if (!h) return RBF_EINVAL;
     h->err.clear();
@@ -1168,35 +1286,50 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
     HIPCHK(h, launch_fill_f64(h->stream, h->N, 0.0, h->ua));
     HIPCHK(h, launch_fill_f64(h->stream, h->N, 0.0, h->ub));
     HIPCHK(h, launch_fill_f64(h->stream, h->N, 0.0, h->fint));
+    HIPCHK(h, launch_fill_f32(h->stream, h->N, 0.0f, h->r32));
     const int reps = 20;
-    float best = 1e30f;
-    SweepCfg bestc = h->cfg;
-    for (int wv : {2, 4, 8})
-        for (int un : {4, 8, 16})
-            for (int rm : {0, 1}) {
-                SweepCfg c;
-                c.waves_per_block = wv;
-                c.unroll = un;
-                c.xcd_remap = rm;
-                HIPCHK(h, launch_sweep_f64(h->stream, c, h->ell, Ni, h->fint, h->ua, h->ub, 0.0, nullptr));
-                HIPCHK(h, hipEventRecord(h->ev0, h->stream));
-                for (int r = 0; r < reps; ++r)
-                    HIPCHK(h, launch_sweep_f64(h->stream, c, h->ell, Ni, h->fint, (r & 1) ? h->ub : h->ua,
-                                               (r & 1) ? h->ua : h->ub, 0.0, nullptr));
-                HIPCHK(h, hipEventRecord(h->ev1, h->stream));
-                HIPCHK(h, hipEventSynchronize(h->ev1));
-                float ms = 0.f;
-                HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
-                if (ms < best) {
-                    best = ms;
-                    bestc = c;
-                }
-            }
-    h->cfg = bestc;
-    char key[160];
-    std::snprintf(key, sizeof key, "sweep|%s|L%d|%" PRId64 "|%" PRId64 "|%d", h->arch, h->ell.layout, Ni, h->ell.elems, h->ell.max_len);
-    int v[3] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap};
-    cache_store(key, v, 3);
+    for (int prec = 0; prec < (h->have_w32 ? 2 : 1); ++prec) {
+        float best = 1e30f;
+        SweepCfg bestc = prec ? h->cfg32 : h->cfg;
+        auto launch = [&](const SweepCfg &c, int r) -> hipError_t {
+            if (prec)
+                return launch_sweep_f32(h->stream, c, h->ell, Ni, h->r32, (r & 1) ? h->eb : h->ea,
+                                        (r & 1) ? h->ea : h->eb, 0.0f);
+            return launch_sweep_f64(h->stream, c, h->ell, Ni, h->fint, (r & 1) ? h->ub : h->ua,
+                                    (r & 1) ? h->ua : h->ub, 0.0, nullptr);
+        };
+        for (int wv : {2, 4, 8})
+            for (int un : {4, 8, 16})
+                for (int rm : {0, 1})
+                    for (int pl : {0, 1}) {
+                        if (pl && h->ell.layout == 0) continue;
+                        SweepCfg c;
+                        c.waves_per_block = wv;
+                        c.unroll = un;
+                        c.xcd_remap = rm;
+                        c.pipeline = pl;
+                        HIPCHK(h, launch(c, 0));
+                        HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+                        for (int r = 0; r < reps; ++r) HIPCHK(h, launch(c, r));
+                        HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+                        HIPCHK(h, hipEventSynchronize(h->ev1));
+                        float ms = 0.f;
+                        HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+                        if (ms < best) {
+                            best = ms;
+                            bestc = c;
+                        }
+                    }
+        (prec ? h->cfg32 : h->cfg) = bestc;
+        char key[160];
+        std::snprintf(key, sizeof key, "%s|%s|L%d|%" PRId64 "|%" PRId64 "|%d", prec ? "sweep32" : "sweep", h->arch,
+                      h->ell.layout, Ni, h->ell.elems, h->ell.max_len);
+        int v[4] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap, bestc.pipeline};
+        cache_store(key, v, 4);
+    }
+    // leave the FP32 work vectors as the mixed loop expects them (0 beyond N_int)
+    HIPCHK(h, launch_fill_f32(h->stream, h->N, 0.0f, h->ea));
+    HIPCHK(h, launch_fill_f32(h->stream, h->N, 0.0f, h->eb));
     return RBF_OK;
 }
 

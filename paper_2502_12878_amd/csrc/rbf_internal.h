@@ -32,8 +32,10 @@ struct SweepCfg {
     int waves_per_block = 4;  // slices (64 rows each) per workgroup
     int unroll = 8;           // support entries loaded ahead per lane
     int xcd_remap = 1;        // give each XCD a contiguous range of slices
+    int pipeline = 0;         // request the next group's streams before the current gathers
     bool operator<(const SweepCfg &o) const {
-        return std::tie(waves_per_block, unroll, xcd_remap) < std::tie(o.waves_per_block, o.unroll, o.xcd_remap);
+        return std::tie(waves_per_block, unroll, xcd_remap, pipeline) <
+               std::tie(o.waves_per_block, o.unroll, o.xcd_remap, o.pipeline);
     }
 };
 
@@ -90,13 +92,15 @@ struct rbf_handle {
     int32_t *perm = nullptr;   // internal -> canonical
     int32_t *iperm = nullptr;  // canonical -> internal
     rbf::Ell ell;
+    rbf::Ell ellT;             // transposed interior operator (built on first use)
 
     // iteration vectors (internal order)
     double *ua = nullptr, *ub = nullptr, *fint = nullptr, *tmp = nullptr, *uref = nullptr;
     double *part = nullptr;   // per-block partial sums
     float *ea = nullptr, *eb = nullptr, *r32 = nullptr;
 
-    rbf::SweepCfg cfg;
+    rbf::SweepCfg cfg;    // FP64 sweep family
+    rbf::SweepCfg cfg32;  // FP32 inner sweeps
     int weights_panel = 32;
     double last_sweep_sec = 0.0;
     int64_t last_sweeps = 0;
@@ -150,7 +154,7 @@ hipError_t launch_weights_items(hipStream_t s, int dim, int64_t N, const double 
                                 const int16_t *nrow, int32_t n_max, const int32_t *rows, const int8_t *mrow,
                                 double *w_out, double *scratch, int64_t slab, int panel, DevStatus *status,
                                 const void *items, int64_t nitems, int32_t *counter, int S_small, int S_mid,
-                                int S_large, int grid, size_t *lds_used);
+                                int S_large, int grid, int nslabs, size_t *lds_used);
 
 // ---------------------------------------------------------------- sweep family
 hipError_t launch_pack_ell(hipStream_t s, int64_t N_int, int32_t n_max, const int32_t *perm, const int32_t *iperm,
@@ -164,6 +168,15 @@ hipError_t launch_apply_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int6
 hipError_t launch_outer_residual(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
                                  const double *u, float *r32, float *e0, unsigned long long *res_slot);
 hipError_t launch_add_correction(hipStream_t s, int64_t N_int, double *u, const float *e);
+hipError_t launch_adjoint_gather(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *lam_old,
+                                 double *lam_new, double *acc, double dt);
+hipError_t launch_tcount(hipStream_t s, int64_t N, int32_t n_max, int64_t N_int, const int8_t *type,
+                         const int32_t *iperm, const int32_t *sten, const int16_t *nrow, int32_t *cnt);
+hipError_t launch_tfill(hipStream_t s, int64_t N, int32_t n_max, int64_t N_int, const int8_t *type,
+                        const int32_t *iperm, const int32_t *sten, const int16_t *nrow, const double *w_can,
+                        const int64_t *start, int32_t *cursor, int32_t *rows_t, double *w_t);
+hipError_t launch_tpack(hipStream_t s, int64_t N_int, const int64_t *start, int32_t *rows_t, double *w_t,
+                        const Ell &e);
 hipError_t launch_err_norm(hipStream_t s, int64_t N, const double *u, const double *uref, double *partials,
                            int nblk, unsigned long long *max_slot);
 hipError_t launch_sum_partials(hipStream_t s, const double *partials, int n, double *out);

@@ -105,6 +105,29 @@ def test_weights_mixed_orders_one_launch():
     assert _rel_rows(wg[I], w[I]) <= 1e-10
 
 
+def test_weights_mixed_orders_with_panel_timing():
+    """Mixed orders with more than 4096 order-6 systems: the solver first times
+    its panel widths on LARGE items only (fewer LDS bytes, more resident
+    workgroups than the full launch), then solves everything.  Regression test
+    for sizing the per-workgroup scratch for the larger of the two grids."""
+    side = 26
+    xyz, typ = ri.jittered_grid(3, side, 0.3, 13)
+    m, n = ri.order_bands(3, xyz, typ, ri.grid_spacing(side), inner=2.0, outer=4.0)
+    assert ((m == 6) & (typ == 0)).sum() >= 4096
+    p = _problem()
+    p.set_nodes(xyz, typ)
+    p.build_stencils(n_per_node=n)
+    p.compute_weights(m_per_node=m)
+    wg = p.get_weights()
+    rng = np.random.default_rng(5)
+    for mm in (2, 4, 6):
+        rows = rng.choice(np.nonzero((m == mm) & (typ == 0))[0], size=20, replace=False)
+        nn = int(n[rows[0]])
+        idx = oracle.knn(xyz, nn, rows)
+        w = oracle.weights(xyz, idx, rows, m=mm)[0]
+        assert _rel_rows(wg[rows, :nn], w) <= 1e-10
+
+
 def _setup_pair(dim, side, m, n, seed, keep_fp32=False, alpha=0.15):
     import torch
     xyz, typ = ri.jittered_grid(dim, side, 0.3, seed)
@@ -216,6 +239,24 @@ def test_transpose_and_adjoint_match_oracle():
     gg = s["p"].adjoint_f(s["dev"](gK), K, every, s["dt"]).cpu().numpy()
     go = s["op"].adjoint_f(s["dt"], K, gK)
     assert np.abs(gg - go).max() <= 1e-11 * np.abs(go).max()
+
+
+def test_transpose_gather_repeatable_and_matches_scatter(monkeypatch):
+    s = _setup_pair(3, 12, 4, 70, 14)
+    rng = np.random.default_rng(8)
+    gK = s["dev"](rng.standard_normal(len(s["typ"])))
+    g1 = s["p"].adjoint_f(gK, 200, 50, s["dt"])
+    g2 = s["p"].adjoint_f(gK, 200, 50, s["dt"])
+    assert (g1 == g2).all()  # gather on the prebuilt transpose: bitwise repeatable
+    t1 = s["p"].apply_transpose(gK)
+    monkeypatch.setenv("RBF_TRANSPOSE_SCATTER", "1")
+    g3 = s["p"].adjoint_f(gK, 200, 50, s["dt"])
+    t3 = s["p"].apply_transpose(gK)
+    monkeypatch.delenv("RBF_TRANSPOSE_SCATTER")
+    assert (g1 - g3).abs().max().item() <= 1e-12 * g1.abs().max().item()
+    assert (t1 - t3).abs().max().item() <= 1e-12 * t1.abs().max().item()
+    go = s["op"].adjoint_f(s["dt"], 200, gK.cpu().numpy())
+    assert np.abs(g1.cpu().numpy() - go).max() <= 1e-11 * np.abs(go).max()
 
 
 def test_forward_checkpoints_resume_bitwise():
