@@ -44,10 +44,18 @@ def lib():
         L.orc_monomials.restype = C.c_int
         L.orc_knn.argtypes = [C.c_int, C.c_int64, _f64p, C.c_int, _i64p, C.c_int64, _i32p]
         L.orc_knn.restype = C.c_int
+        L.orc_knn_typed.argtypes = [C.c_int, C.c_int64, _f64p, C.c_int, _i64p, C.c_int64, C.c_void_p, _i32p]
+        L.orc_knn_typed.restype = C.c_int
         L.orc_weights.argtypes = [C.c_int, C.c_int64, _f64p, _i64p, C.c_int64, _i32p, C.c_int,
                                   C.c_void_p, C.c_int, C.c_void_p, _f64p, _f64p,
                                   C.POINTER(C.c_int64)]
         L.orc_weights.restype = C.c_int
+        L.orc_weights_op.argtypes = [C.c_int, C.c_int64, _f64p, _i64p, C.c_int64, _i32p, C.c_int,
+                                     C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, _f64p, _f64p,
+                                     C.POINTER(C.c_int64)]
+        L.orc_weights_op.restype = C.c_int
+        L.orc_neumann_update.argtypes = [C.c_int64, _i8p, _i32p, _f64p, C.c_int, C.c_void_p, _f64p, _f64p]
+        L.orc_neumann_update.restype = None
         L.orc_assemble.argtypes = [C.c_int, C.c_int64, _f64p, C.c_int64, _i32p, C.c_int, C.c_int,
                                    _f64p, C.POINTER(C.c_double)]
         L.orc_assemble.restype = C.c_int
@@ -92,13 +100,15 @@ def monomials(dim: int, m: int) -> np.ndarray:
     return out
 
 
-def knn(xyz: np.ndarray, n: int, rows=None) -> np.ndarray:
-    """Brute-force supports: for each centre, the n smallest (d^2, id)."""
+def knn(xyz: np.ndarray, n: int, rows=None, typ=None) -> np.ndarray:
+    """Brute-force supports: for each centre, the n smallest (d^2, id); with
+    ``typ``, Neumann centres (type 2) take only themselves and interior nodes."""
     xyz = _c(xyz, np.float64)
     dim, N = xyz.shape
     rows = np.arange(N, dtype=np.int64) if rows is None else _c(rows, np.int64)
     out = np.zeros((len(rows), n), dtype=np.int32)
-    st = lib().orc_knn(dim, N, xyz.reshape(-1), n, rows, len(rows), out.reshape(-1))
+    typ_a = None if typ is None else _c(typ, np.int8)
+    st = lib().orc_knn_typed(dim, N, xyz.reshape(-1), n, rows, len(rows), _ptr_or_none(typ_a), out.reshape(-1))
     if st != 0:
         raise ValueError(f"orc_knn status {st}")
     return out
@@ -127,8 +137,9 @@ class SingularSystem(RuntimeError):
 
 
 def weights(xyz: np.ndarray, stencils: np.ndarray, rows, m=None, m_row=None, n_row=None,
-            raise_on_singular: bool = True):
-    """RBF-FD Laplacian weights for centres ``rows`` with supports ``stencils``.
+            raise_on_singular: bool = True, op_row=None, normals=None):
+    """RBF-FD weights for centres ``rows`` with supports ``stencils``: the
+    Laplacian, or (op_row[q] = 1) the derivative along ``normals[:, rows[q]]``.
 
     Returns (w [rows, n], pivot_ratio [rows], status, bad_row).
     """
@@ -140,12 +151,15 @@ def weights(xyz: np.ndarray, stencils: np.ndarray, rows, m=None, m_row=None, n_r
     assert nr == len(rows)
     nrow_a = None if n_row is None else _c(n_row, np.int32)
     mrow_a = None if m_row is None else _c(m_row, np.int8)
+    op_a = None if op_row is None else _c(op_row, np.int8)
+    nv_a = None if normals is None else _c(normals, np.float64)
     w = np.zeros((nr, ns), dtype=np.float64)
     pr = np.zeros(nr, dtype=np.float64)
     bad = C.c_int64(-1)
-    st = lib().orc_weights(dim, N, xyz.reshape(-1), rows, nr, st_.reshape(-1), ns,
-                           _ptr_or_none(nrow_a), int(m if m is not None else 0),
-                           _ptr_or_none(mrow_a), w.reshape(-1), pr, C.byref(bad))
+    st = lib().orc_weights_op(dim, N, xyz.reshape(-1), rows, nr, st_.reshape(-1), ns,
+                              _ptr_or_none(nrow_a), int(m if m is not None else 0),
+                              _ptr_or_none(mrow_a), _ptr_or_none(op_a), _ptr_or_none(nv_a),
+                              w.reshape(-1), pr, C.byref(bad))
     if st == 3 and raise_on_singular:
         raise SingularSystem(bad.value)
     if st not in (0, 3):
@@ -182,7 +196,8 @@ class Operator:
 
     def sweep(self, f, dt, u_old):
         u_new = np.empty(self.N)
-        res = lib().orc_sweep(*self._common(), _c(f, np.float64), float(dt), _c(u_old, np.float64), u_new)
+        u_in = np.array(u_old, dtype=np.float64)  # the Neumann update writes into the old state
+        res = lib().orc_sweep(*self._common(), _c(f, np.float64), float(dt), u_in, u_new)
         return u_new, res
 
     def sweep_omp(self, f, dt, u_old, u_new, nthreads):
@@ -223,8 +238,9 @@ class Operator:
         return grad
 
 
-def setup(xyz, typ, n, m=None, n_row=None, m_row=None):
-    """Supports for every node and weights for every interior node.
+def setup(xyz, typ, n, m=None, n_row=None, m_row=None, normals=None):
+    """Supports for every node; Laplacian weights for every interior node and,
+    with ``normals``, normal-derivative weights for every Neumann node (type 2).
 
     Returns (idx [N, n_max], w [N, n_max]); Dirichlet rows of w are zero.
     With per-node sizes, row r of idx holds its n_row[r] nearest nodes and is
@@ -233,8 +249,9 @@ def setup(xyz, typ, n, m=None, n_row=None, m_row=None):
     xyz = _c(xyz, np.float64)
     N = xyz.shape[1]
     typ = _c(typ, np.int8)
+    ktyp = typ if normals is not None else None
     if n_row is None:
-        idx = knn(xyz, n)
+        idx = knn(xyz, n, typ=ktyp)
         n_max = n
     else:
         n_row = _c(n_row, np.int32)
@@ -242,11 +259,16 @@ def setup(xyz, typ, n, m=None, n_row=None, m_row=None):
         idx = np.repeat(np.arange(N, dtype=np.int32)[:, None], n_max, axis=1)
         for nn in np.unique(n_row):
             sel = np.nonzero(n_row == nn)[0]
-            idx[sel, :nn] = knn(xyz, int(nn), sel)
-    interior = np.nonzero(typ == 0)[0].astype(np.int64)
+            idx[sel, :nn] = knn(xyz, int(nn), sel, typ=ktyp)
     w = np.zeros((N, n_max))
-    wi, _, _, _ = weights(xyz, idx[interior], interior, m=m,
-                          m_row=None if m_row is None else np.asarray(m_row)[interior],
-                          n_row=None if n_row is None else n_row[interior])
-    w[interior] = wi
+    for code, op in ((0, 0), (2, 1)):
+        rows = np.nonzero(typ == code)[0].astype(np.int64)
+        if len(rows) == 0:
+            continue
+        wi, _, _, _ = weights(xyz, idx[rows], rows, m=m,
+                              m_row=None if m_row is None else np.asarray(m_row)[rows],
+                              n_row=None if n_row is None else n_row[rows],
+                              op_row=np.full(len(rows), op, dtype=np.int8) if op else None,
+                              normals=normals if op else None)
+        w[rows] = wi
     return idx, w

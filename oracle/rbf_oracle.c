@@ -83,16 +83,21 @@ static double sqdist(int dim, int64_t N, const double *xyz, int64_t j, int64_t c
 /* with the smallest keys (d2, id) in lexicographic order, listed in         */
 /* ascending key order.  The centre itself has d2 = 0 and comes first.       */
 /* ------------------------------------------------------------------------ */
-int orc_knn(int dim, int64_t N, const double *xyz, int n,
-            const int64_t *rows, int64_t nrows, int32_t *out /* [nrows][n] */)
+/* With `type` given, a Neumann centre (type 2) draws its support from itself
+ * and the interior nodes only (Sec. II-C: boundary values are computed from
+ * the interior values of the last step in the boundary node's support). */
+int orc_knn_typed(int dim, int64_t N, const double *xyz, int n, const int64_t *rows, int64_t nrows,
+                  const int8_t *type, int32_t *out)
 {
     if (dim < 1 || dim > 3 || n < 1 || n > N) return ORC_EINVAL;
     double *bd = (double *)malloc(sizeof(double) * (size_t)n);
     int64_t *bi = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     for (int64_t q = 0; q < nrows; ++q) {
         int64_t c = rows[q];
+        int restrict_interior = type && type[c] == 2;
         int cnt = 0;
         for (int64_t j = 0; j < N; ++j) {
+            if (restrict_interior && j != c && type[j] != 0) continue;
             double d2 = sqdist(dim, N, xyz, j, c);
             /* keep the n smallest (d2, j); j ascends, so a new key never
              * beats an equal-distance key already held */
@@ -107,11 +112,18 @@ int orc_knn(int dim, int64_t N, const double *xyz, int n,
             bi[pos] = j;
             if (cnt < n) ++cnt;
         }
+        if (cnt < n) { free(bd); free(bi); return ORC_EINVAL; }
         for (int k = 0; k < n; ++k) out[q * n + k] = (int32_t)bi[k];
     }
     free(bd);
     free(bi);
     return ORC_OK;
+}
+
+int orc_knn(int dim, int64_t N, const double *xyz, int n,
+            const int64_t *rows, int64_t nrows, int32_t *out /* [nrows][n] */)
+{
+    return orc_knn_typed(dim, N, xyz, n, rows, nrows, NULL, out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -130,11 +142,19 @@ int orc_knn(int dim, int64_t N, const double *xyz, int n,
 /* the largest entry of the assembled matrix.  *pivot_ratio receives        */
 /* min|pivot| / max|a| (a conditioning diagnostic).                          */
 /* ------------------------------------------------------------------------ */
+/* The same system for the derivative along a unit normal nv at the centre
+ * (the Neumann rows of the mixed-boundary variant, Sec. II-C): the right-hand
+ * side becomes (dPhi/dn)_k = 3|y_k| ((0 - y_k) . nv), the derivative of
+ * |y - y_k|^3 at y = 0, and (dp/dn)_j = nv_a for the linear monomial y_a, 0
+ * otherwise; the weights in x are w_k = x_k / s (degree -1).             */
+/* ------------------------------------------------------------------------ */
 /* Assemble the augmented matrix [A P b1; P^T 0 b2] (S rows, S+1 columns,
- * row-major, S = n + M) for centre c.  Returns the scale s (0 if all support
- * nodes coincide with the centre). */
+ * row-major, S = n + M) for centre c; op 0 = Laplacian, op 1 = derivative
+ * along nv.  Returns the scale s (0 if all support nodes coincide with the
+ * centre). */
 static double assemble(int dim, int64_t N, const double *xyz, int64_t c,
-                       const int32_t *sten, int n, int m, double *a, double *y)
+                       const int32_t *sten, int n, int m, int op, const double *nv,
+                       double *a, double *y)
 {
     int exps[84 * 3];
     int M = orc_monomials(dim, m, exps);
@@ -179,12 +199,29 @@ static double assemble(int dim, int64_t N, const double *xyz, int64_t c,
             double t2 = y[3 * k + ax] * y[3 * k + ax];
             r2 = (ax == 0) ? t2 : r2 + t2;
         }
-        a[k * C + S] = c3 * sqrt(r2);
+        if (op == 0) {
+            a[k * C + S] = c3 * sqrt(r2);
+        } else {
+            double dn = 0.0; /* (0 - y_k) . nv */
+            for (int ax = 0; ax < dim; ++ax) {
+                double t = (0.0 - y[3 * k + ax]) * nv[ax];
+                dn = (ax == 0) ? t : dn + t;
+            }
+            a[k * C + S] = (3.0 * sqrt(r2)) * dn;
+        }
     }
     for (int j = 0; j < M; ++j) {
         int deg = exps[3 * j] + exps[3 * j + 1] + exps[3 * j + 2];
-        int pure = (exps[3 * j] == 2 || exps[3 * j + 1] == 2 || exps[3 * j + 2] == 2);
-        a[(n + j) * C + S] = (deg == 2 && pure) ? 2.0 : 0.0;
+        if (op == 0) {
+            int pure = (exps[3 * j] == 2 || exps[3 * j + 1] == 2 || exps[3 * j + 2] == 2);
+            a[(n + j) * C + S] = (deg == 2 && pure) ? 2.0 : 0.0;
+        } else {
+            double v = 0.0;
+            if (deg == 1)
+                for (int ax = 0; ax < dim; ++ax)
+                    if (exps[3 * j + ax] == 1) v = nv[ax];
+            a[(n + j) * C + S] = v;
+        }
     }
     return s;
 }
@@ -195,12 +232,12 @@ int orc_assemble(int dim, int64_t N, const double *xyz, int64_t c, const int32_t
 {
     double y[3 * 512];
     if (dim < 1 || dim > 3 || n < 1 || n > 512 || m < 0 || m > 6) return ORC_EINVAL;
-    *s_out = assemble(dim, N, xyz, c, sten, n, m, a_out, y);
+    *s_out = assemble(dim, N, xyz, c, sten, n, m, 0, NULL, a_out, y);
     return ORC_OK;
 }
 
 static int weights_one(int dim, int64_t N, const double *xyz, int64_t c,
-                       const int32_t *sten, int n, int m,
+                       const int32_t *sten, int n, int m, int op, const double *nv,
                        double *w_out, double *pivot_ratio, double *work)
 {
     int M = orc_monomials(dim, m, NULL);
@@ -209,7 +246,7 @@ static int weights_one(int dim, int64_t N, const double *xyz, int64_t c,
     double *a = work;             /* [S][C] */
     double *y = work + S * C;     /* [n][3] */
     double *x = y + 3 * n;        /* [S]    */
-    double s = assemble(dim, N, xyz, c, sten, n, m, a, y);
+    double s = assemble(dim, N, xyz, c, sten, n, m, op, nv, a, y);
     if (!(s > 0.0)) { *pivot_ratio = 0.0; return ORC_ESINGULAR; }
 
     double amax = 0.0;
@@ -255,7 +292,7 @@ static int weights_one(int dim, int64_t N, const double *xyz, int64_t c,
             a[i * C + S] = a[i * C + S] - prod;
         }
     }
-    double s2 = s * s;
+    double s2 = (op == 0) ? s * s : s;
     for (int k = 0; k < n; ++k) w_out[k] = x[k] / s2;
     *pivot_ratio = (amax > 0.0) ? pmin / amax : 0.0;
     return ORC_OK;
@@ -263,13 +300,15 @@ static int weights_one(int dim, int64_t N, const double *xyz, int64_t c,
 
 /* Weights for a list of centres.  stencils: [nrows][n_stride], row q holding
  * n_row[q] entries (n_row NULL -> all n_stride); m_row likewise (NULL -> m).
+ * op_row[q] (NULL -> all 0) selects the operator: 0 Laplacian, 1 derivative
+ * along normals[:, rows[q]] (normals: [dim][N]).
  * w_out: [nrows][n_stride], entries beyond n_row[q] set to 0.
  * On a singular system returns 3 and writes the centre id to *bad_row. */
-int orc_weights(int dim, int64_t N, const double *xyz,
-                const int64_t *rows, int64_t nrows,
-                const int32_t *stencils, int n_stride, const int32_t *n_row,
-                int m, const int8_t *m_row,
-                double *w_out, double *pivot_ratio_out, int64_t *bad_row)
+int orc_weights_op(int dim, int64_t N, const double *xyz,
+                   const int64_t *rows, int64_t nrows,
+                   const int32_t *stencils, int n_stride, const int32_t *n_row,
+                   int m, const int8_t *m_row, const int8_t *op_row, const double *normals,
+                   double *w_out, double *pivot_ratio_out, int64_t *bad_row)
 {
     if (dim < 1 || dim > 3 || n_stride < 1) return ORC_EINVAL;
     int S_max = n_stride + 84;
@@ -281,13 +320,29 @@ int orc_weights(int dim, int64_t N, const double *xyz,
         double pr = 0.0;
         for (int k = 0; k < n_stride; ++k) w_out[q * n_stride + k] = 0.0;
         if (n < 1 || n > n_stride || mm < 0 || mm > 6) { status = ORC_EINVAL; if (bad_row) *bad_row = rows[q]; break; }
-        int st = weights_one(dim, N, xyz, rows[q], stencils + q * n_stride, n, mm,
+        int op = op_row ? op_row[q] : 0;
+        double nv[3] = {0.0, 0.0, 0.0};
+        if (op == 1) {
+            if (!normals) { status = ORC_EINVAL; if (bad_row) *bad_row = rows[q]; break; }
+            for (int ax = 0; ax < dim; ++ax) nv[ax] = normals[ax * N + rows[q]];
+        }
+        int st = weights_one(dim, N, xyz, rows[q], stencils + q * n_stride, n, mm, op, nv,
                              w_out + q * n_stride, &pr, work);
         if (pivot_ratio_out) pivot_ratio_out[q] = pr;
         if (st != ORC_OK) { status = st; if (bad_row) *bad_row = rows[q]; break; }
     }
     free(work);
     return status;
+}
+
+int orc_weights(int dim, int64_t N, const double *xyz,
+                const int64_t *rows, int64_t nrows,
+                const int32_t *stencils, int n_stride, const int32_t *n_row,
+                int m, const int8_t *m_row,
+                double *w_out, double *pivot_ratio_out, int64_t *bad_row)
+{
+    return orc_weights_op(dim, N, xyz, rows, nrows, stencils, n_stride, n_row, m, m_row, NULL, NULL,
+                          w_out, pivot_ratio_out, bad_row);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -322,13 +377,46 @@ void orc_apply(int64_t N, const int8_t *type, const int32_t *idx, const double *
     }
 }
 
-/* One explicit step u_new = u_old + dt (L u_old - f) on interior rows;
- * Dirichlet rows copy u_old.  Returns max |L u_old - f| over interior rows
- * (the residual of u_old). */
+/* Neumann boundary update (Sec. II-C, the paragraph on enforcing the Neumann
+ * condition): before a step, every Neumann node b (type 2) takes the value for
+ * which its normal-derivative stencil returns the prescribed data f_b, with
+ * the other nodes of its support at their previous-step values:
+ *   u_b = (f_b - sum_{k: idx_bk != b} w_bk u_{idx_bk}) / w_bb.
+ * All new values are computed from the old ones before any is stored. */
+void orc_neumann_update(int64_t N, const int8_t *type, const int32_t *idx, const double *w,
+                        int n_stride, const int32_t *n_row, const double *f, double *u)
+{
+    int64_t nn = 0;
+    for (int64_t r = 0; r < N; ++r) nn += type[r] == 2;
+    if (!nn) return;
+    double *nb = (double *)malloc(sizeof(double) * (size_t)nn);
+    int64_t q = 0;
+    for (int64_t r = 0; r < N; ++r) {
+        if (type[r] != 2) continue;
+        int n = n_row ? n_row[r] : n_stride;
+        double acc = 0.0, self = 0.0;
+        for (int k = 0; k < n; ++k) {
+            int32_t j = idx[r * n_stride + k];
+            if (j == r) { self = w[r * n_stride + k]; continue; }
+            double prod = w[r * n_stride + k] * u[j];
+            acc = acc + prod;
+        }
+        nb[q++] = (f[r] - acc) / self;
+    }
+    q = 0;
+    for (int64_t r = 0; r < N; ++r)
+        if (type[r] == 2) u[r] = nb[q++];
+    free(nb);
+}
+
+/* One explicit step u_new = u_old + dt (L u_old - f) on interior rows, after
+ * the Neumann update of u_old; Dirichlet and Neumann rows copy u_old.  Returns
+ * max |L u_old - f| over interior rows (the residual of u_old). */
 double orc_sweep(int64_t N, const int8_t *type, const int32_t *idx, const double *w,
                  int n_stride, const int32_t *n_row, const double *f, double dt,
-                 const double *u_old, double *u_new)
+                 double *u_old, double *u_new)
 {
+    orc_neumann_update(N, type, idx, w, n_stride, n_row, f, u_old);
     double res = 0.0;
     for (int64_t r = 0; r < N; ++r) {
         if (type[r] != 0) { u_new[r] = u_old[r]; continue; }

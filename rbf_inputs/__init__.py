@@ -115,6 +115,55 @@ def manufactured(dim: int, xyz: np.ndarray, typ: np.ndarray):
     return u, f, g, u0
 
 
+NEUMANN = 2
+
+
+def mixed_bc_grid(dim: int, side: int, jitter_frac: float, seed: int):
+    """Node set of the mixed-boundary variant (Sec. II-C, second paragraph):
+    the sub-cube [0, 1/2]^dim, sampled by the unit-cube jittered grid scaled by
+    1/2 (exact in binary floating point).  Nodes with a grid index 0 are
+    Dirichlet (faces on the original boundary, u = 0); the remaining nodes with
+    a grid index side-1 are Neumann (faces inside the original cube, where the
+    normal derivative of u is 0).  Their outward unit normal is the normalised
+    sum of the unit normals of the faces they lie on.
+
+    Returns xyz [dim, N], type int8 [N] (0 interior, 1 Dirichlet, 2 Neumann)
+    and normals [dim, N] (zero except on Neumann nodes).
+    """
+    xyz, typ = jittered_grid(dim, side, jitter_frac, seed)
+    xyz = xyz * 0.5
+    N = side ** dim
+    ids = np.arange(N, dtype=np.int64)
+    lo = np.zeros(N, dtype=bool)
+    hi = np.zeros((dim, N), dtype=bool)
+    rem = ids.copy()
+    for a in range(dim):
+        gi = rem % side
+        rem //= side
+        lo |= gi == 0
+        hi[a] = gi == side - 1
+    typ = np.where(lo, DIRICHLET, np.where(hi.any(axis=0), NEUMANN, INTERIOR)).astype(np.int8)
+    normals = np.where((typ == NEUMANN)[None, :], hi.astype(np.float64), 0.0)
+    cnt = hi.sum(axis=0)
+    normals = np.where(cnt[None, :] > 0, normals / np.sqrt(np.maximum(cnt, 1))[None, :], 0.0)
+    normals[:, typ != NEUMANN] = 0.0
+    return xyz, typ, normals
+
+
+def manufactured_mixed(dim: int, xyz: np.ndarray, typ: np.ndarray):
+    """u = prod sin(pi x_i) on [0, 1/2]^d: Laplacian u = f inside, u = g = 0 on
+    the Dirichlet faces, normal derivative 0 on the Neumann faces.  Returns
+    (u_exact, f, u0) where f holds -pi^2 d u on interior nodes and the normal
+    derivative data (0) on Neumann nodes; u0 is 0 except g on Dirichlet nodes."""
+    u = np.ones(xyz.shape[1], dtype=np.float64)
+    for a in range(dim):
+        u = u * np.sin(math.pi * xyz[a])
+    c = dim * math.pi * math.pi
+    f = np.where(typ == INTERIOR, -c * u, 0.0)
+    u0 = np.where(typ == DIRICHLET, u, 0.0)
+    return u, f, u0
+
+
 def gaussian_params(dim: int, seed: int, count: int = 16):
     """Parameters of a sum of ``count`` Gaussians drawn from SplitMix64 ``seed``.
 
