@@ -194,7 +194,8 @@ def run_cube8m(mode_name, target, piece_steps=40000, max_steps=3_000_000):
         steps += rep["steps"]
         dev_s += rep["seconds"]
         _progress(f"cube8M {mode_name}: {steps} steps, err_inf {rep['err_inf']:.3e}, device {dev_s:.1f} s")
-        if st != 0 or rep["err_met"]:
+        # a piece that ends before the target reports "not converged" (5); go on
+        if rep["err_met"] or st not in (0, 5):
             break
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
@@ -320,6 +321,48 @@ def run_cube2m_adjoint(directions=32):
             "median_rel_err_vs_fd": float(np.median(errs)), "rel_errs": errs}
 
 
+def run_support_sweep(m=2, sizes=(20, 30, 40, 60, 80, 100, 130, 168), steps=1000):
+    """Support size beyond 2M at fixed order (the compute-time model t ~ n of
+    the paper's support-size study): sweep time, node-updates/s and algorithmic
+    GB/s per n on the 1M-node cube, plus the truncation error
+    max |L_h u_exact - f| of each operator."""
+    import numpy as np
+    import torch
+
+    import rbf_inputs as ri
+    from paper_2502_12878_amd import Problem
+    wl = ri.workload("cube1M", m=m)
+    xyz_h, typ_h = wl.nodes()
+    u_ex, f, g, u0 = ri.manufactured(3, xyz_h, typ_h)
+    nint = int((typ_h == 0).sum())
+    rows = []
+    for n in sizes:
+        p = Problem(0)
+        xd, td = p.build_nodes(3, wl.side, wl.jitter, wl.seed)
+        p.set_nodes(xd, td)
+        del xd, td
+        t0 = time.perf_counter()
+        p.build_stencils(n)
+        p.compute_weights(m)
+        setup = time.perf_counter() - t0
+        p.autotune()
+        s = {"p": p, "wl": wl, "f": _dev(f), "u0": _dev(u0)}
+        wall, per_sweep, nsw, rep = time_sweeps(s, steps, 100)
+        trunc = p.residual(s["f"], _dev(u_ex))
+        rows.append({"n": n, "setup_s": round(setup, 3), "kernel_ms_per_sweep": round(1e3 * per_sweep, 4),
+                     "node_updates_per_s": nint / per_sweep,
+                     "alg_GBps": round(nint * (12 * n + 24) / per_sweep / 1e9, 1), "truncation_err_inf": trunc})
+        _progress(f"n={n}: {1e3 * per_sweep:.4f} ms per sweep, truncation {trunc:.3e}")
+        p.close()
+    ns = np.array([r["n"] for r in rows], dtype=float)
+    ts = np.array([r["kernel_ms_per_sweep"] for r in rows])
+    slope = float(np.polyfit(np.log(ns), np.log(ts), 1)[0])
+    a, b = np.polyfit(12 * ns + 24, ts, 1)
+    return {"workload": f"cube1M support sweep: 3D 100^3 jittered grid (seed 1), m={m}, n in {list(sizes)}",
+            "interior_nodes": nint, "rows": rows, "loglog_slope_t_vs_n": round(slope, 3),
+            "fit_ms_per_byte_per_row": a, "fit_ms_offset": b}
+
+
 def stream_ceiling(nbytes=1 << 30, reps=20):
     """Achievable HBM rates on this device for context: a 1 GiB device copy
     (read + write) and a 1 GiB read-only sum, timed with events."""
@@ -366,7 +409,7 @@ def main():
     ap.add_argument("--tte-target", type=float, default=1e-6)
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--workload", default="cube1M",
-                    choices=["cube1M", "cube8M", "cube4M_bands", "cube2M_adjoint"],
+                    choices=["cube1M", "cube8M", "cube4M_bands", "cube2M_adjoint", "support_sweep"],
                     help="cube1M: the benchmark line; the others print their own measurement line")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32_refine"], help="cube8M: iteration mode")
     args = ap.parse_args()
@@ -385,6 +428,8 @@ def main():
             out = run_cube8m(args.mode, args.tte_target)
         elif args.workload == "cube4M_bands":
             out = run_cube4m_bands()
+        elif args.workload == "support_sweep":
+            out = run_support_sweep()
         else:
             out = run_cube2m_adjoint()
         out["device"] = torch.cuda.get_device_name(0)

@@ -27,7 +27,8 @@
  *   array crossing the ABI is in canonical order.  The library may renumber
  *   internally; that never shows at the ABI.
  * - Coordinates are structure-of-arrays: xyz[a*N + i] is coordinate a of
- *   node i.  Node types: 0 interior, 1 Dirichlet.
+ *   node i.  Node types: 0 interior, 1 Dirichlet, 2 Neumann (the mixed
+ *   boundary variant of Sec. II-C; Neumann nodes need unit outward normals).
  * - One host thread at a time per handle.
  */
 #ifndef RBF_MI355X_H
@@ -98,8 +99,16 @@ rbf_status rbf_build_nodes(rbf_handle *h, int dim, int64_t side, double jitter_f
                            double *xyz_dev, int8_t *type_dev);
 
 /* Give the handle its node set (copied).  Resets stencils and weights.
- * EINVAL: dim not in 1..3, N < 1 or N > 2^31-1, NULL pointers. */
+ * EINVAL: dim not in 1..3, N < 1 or N > 2^31-1, a type other than 0/1/2,
+ * NULL pointers. */
 rbf_status rbf_set_nodes(rbf_handle *h, int dim, int64_t N, const double *xyz_dev, const int8_t *type_dev);
+
+/* Unit outward normals of the Neumann nodes (Sec. II-C, mixed boundary
+ * conditions): normals_dev [dim][N] doubles (entries of other nodes are
+ * ignored), copied.  Required before rbf_compute_weights when Neumann nodes
+ * exist.  EINVAL: no nodes, a Neumann normal whose length differs from 1 by
+ * more than 1e-12. */
+rbf_status rbf_set_normals(rbf_handle *h, const double *normals_dev);
 
 /* --------------------------------------------------------- build stencils */
 
@@ -107,7 +116,9 @@ rbf_status rbf_set_nodes(rbf_handle *h, int dim, int64_t N, const double *xyz_de
  * node, its n nearest nodes, the node itself first, in ascending order of the
  * key (d2, id) with d2 = (dx*dx + dy*dy) + dz*dz, dx = x_j - x_c, each
  * operation rounded separately; ties go to the lower id.  The search bins
- * nodes into a uniform cell grid and is exact.
+ * nodes into a uniform cell grid and is exact.  A Neumann node's support is
+ * itself and its nearest interior nodes (its boundary value is computed from
+ * interior values only, Sec. II-C).
  * n_uniform: support size for every node, or 0 with n_per_node_dev
  * ([N] int16, device) giving each node's size.  Synchronises.
  * EINVAL: n < 1 or n > N or n > 256; EOVERFLOW: a node's candidate set
@@ -122,7 +133,9 @@ rbf_status rbf_build_stencils(rbf_handle *h, int32_t n_uniform, const int16_t *n
  * (M = C(m+d, d), graded, x exponent then y exponent descending).  The system
  * is built in local coordinates y = (x - x_c)/s, s = the largest support
  * distance, solved in FP64 by Gaussian elimination with partial pivoting
- * (first row of largest |a_ik|), and w = x/(s*s).
+ * (first row of largest |a_ik|), and w = x/(s*s).  Neumann rows get the
+ * weights of the derivative along their normal nv instead: right-hand side
+ * 3|y_k| ((0 - y_k) . nv) and nv_a for the monomial y_a, w = x/s.
  * m_uniform: order for every node, or -1 with m_per_node_dev ([N] int8).
  * keep_fp32: also keep an FP32 copy (needed by the mixed-precision mode).
  * Synchronises.  ESINGULAR (with the node id in rbf_last_error) when a pivot
@@ -179,13 +192,20 @@ typedef struct {
  * Mixed mode: per outer pass r = f - L64 u (FP64 weights), then inner_steps
  * FP32 steps e <- e + dt (L32 e - (float)r) from e = 0 with FP32 weights and
  * accumulation, then u += e.  Requires keep_fp32 at rbf_compute_weights.
+ * Neumann nodes: f_dev on a Neumann node is its prescribed normal
+ * derivative g_b.  Before every step each Neumann node takes
+ * u_b = (g_b - sum_{k != b} w_bk u_k) / w_bb with the other support values of
+ * the current iterate (all new values are computed before any is stored).
+ * Mixed precision is implemented for problems without Neumann nodes only
+ * (EINVAL).
  * Synchronises; the report is filled on every return path except EINVAL. */
 rbf_status rbf_iterate(rbf_handle *h, const double *f_dev, double *u_dev, const rbf_iter_params *p,
                        rbf_iter_report *report);
 
 /* ------------------------------------------------ single operator calls */
 
-/* Lu_dev[r] = sum_k w_rk u_dev[idx_rk] for interior r; 0 on Dirichlet rows. */
+/* Lu_dev[r] = sum_k w_rk u_dev[idx_rk] for interior r (the Laplacian) and for
+ * Neumann r (the normal derivative); 0 on Dirichlet rows. */
 rbf_status rbf_apply(rbf_handle *h, const double *u_dev, double *Lu_dev);
 
 /* out_dev[c] = sum over interior rows r and support entries k with
@@ -216,7 +236,7 @@ rbf_status rbf_forward_ckpt(rbf_handle *h, const double *f_dev, const double *u0
  * be NULL because this gradient does not depend on the states.  Each
  * transposed step is a gather sweep over L_II^T (built once, deterministic;
  * RBF_TRANSPOSE_SCATTER=1 selects the atomic scatter as for
- * rbf_apply_transpose). */
+ * rbf_apply_transpose).  EINVAL when the node set has Neumann nodes. */
 rbf_status rbf_adjoint_f(rbf_handle *h, const double *gK_dev, int64_t K, int64_t every,
                          const double *ckpt_dev, double *grad_f_dev, double dt);
 

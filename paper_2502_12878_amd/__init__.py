@@ -108,6 +108,11 @@ class Problem:
         dim, N = xyz.shape
         self._check(self._lib.rbf_set_nodes(self.h, dim, N, _ptr(xyz), _ptr(typ)), "set_nodes")
 
+    def set_normals(self, normals):
+        """Unit outward normals [dim, N] of the Neumann nodes (type 2)."""
+        nv = self._cuda(normals, self.torch.float64)
+        self._check(self._lib.rbf_set_normals(self.h, _ptr(nv)), "set_normals")
+
     # ------------------------------------------------------------------ stencils and weights
     def build_stencils(self, n=None, n_per_node=None):
         torch = self.torch

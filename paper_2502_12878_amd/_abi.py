@@ -59,6 +59,7 @@ SIGNATURES = {
                             C.POINTER(C.c_int32)]),
     "rbf_build_nodes": (_st, [_h, C.c_int, C.c_int64, C.c_double, C.c_uint64, _p, _p]),
     "rbf_set_nodes": (_st, [_h, C.c_int, C.c_int64, _p, _p]),
+    "rbf_set_normals": (_st, [_h, _p]),
     "rbf_build_stencils": (_st, [_h, C.c_int32, _p]),
     "rbf_compute_weights": (_st, [_h, C.c_int32, _p, C.c_int]),
     "rbf_iterate": (_st, [_h, _p, _p, C.POINTER(rbf_iter_params), C.POINTER(rbf_iter_report)]),

@@ -194,7 +194,8 @@ __global__ __launch_bounds__(64) void k_knn(CellGrid g, int64_t N, const double 
                                             const int32_t *__restrict__ cstart, const int32_t *__restrict__ ids_c,
                                             int32_t n_uniform, const int16_t *__restrict__ n_per_node, int32_t n_max,
                                             double ball_coef, double margin, int32_t *__restrict__ sten,
-                                            int16_t *__restrict__ nrow_out, DevStatus *status) {
+                                            int16_t *__restrict__ nrow_out, const int8_t *__restrict__ type,
+                                            DevStatus *status) {
     __shared__ unsigned long long kd[kCap];
     __shared__ int32_t kid[kCap];
     __shared__ int32_t row_p0[kMaxRows];
@@ -205,6 +206,8 @@ __global__ __launch_bounds__(64) void k_knn(CellGrid g, int64_t N, const double 
     const int lane = threadIdx.x;
     const int dim = g.dim;
     const int n = n_per_node ? (int)n_per_node[q] : n_uniform;
+    // a Neumann node (type 2) draws its support from itself and interior nodes
+    const bool interior_only = type[q] == 2;
     double xq[3] = {0.0, 0.0, 0.0};
     int qc[3] = {0, 0, 0};
     for (int a = 0; a < dim; ++a) {
@@ -283,10 +286,13 @@ __global__ __launch_bounds__(64) void k_knn(CellGrid g, int64_t N, const double 
             const double d2 = sq_dist(dim, xq, xyz_c[p], dim > 1 ? xyz_c[N + p] : 0.0,
                                       dim > 2 ? xyz_c[2 * N + p] : 0.0);
             if (d2 < bound2) {
-                const int slot = atomicAdd(&s_count, 1);
-                if (slot < kCap) {
-                    kd[slot] = (unsigned long long)__double_as_longlong(d2);
-                    kid[slot] = ids_c[p];
+                const int32_t j = ids_c[p];
+                if (!interior_only || j == q || type[j] == 0) {
+                    const int slot = atomicAdd(&s_count, 1);
+                    if (slot < kCap) {
+                        kd[slot] = (unsigned long long)__double_as_longlong(d2);
+                        kid[slot] = j;
+                    }
                 }
             }
         }
@@ -373,9 +379,10 @@ hipError_t launch_coords_by_cell(hipStream_t s, int dim, int64_t N, const double
 hipError_t launch_knn_query(hipStream_t s, const CellGrid &g, int64_t N, const double *xyz, const double *xyz_c,
                             const int32_t *cell_of, const int32_t *cell_start, const int32_t *ids_by_cell,
                             int32_t n_uniform, const int16_t *n_per_node, int32_t n_max, double ball_coef,
-                            double margin, int32_t *sten, int16_t *nrow_out, DevStatus *status) {
+                            double margin, int32_t *sten, int16_t *nrow_out, const int8_t *type,
+                            DevStatus *status) {
     hipLaunchKernelGGL(k_knn, dim3((unsigned)N), dim3(64), 0, s, g, N, xyz, xyz_c, cell_of, cell_start, ids_by_cell,
-                       n_uniform, n_per_node, n_max, ball_coef, margin, sten, nrow_out, status);
+                       n_uniform, n_per_node, n_max, ball_coef, margin, sten, nrow_out, type, status);
     return hipGetLastError();
 }
 

@@ -393,12 +393,15 @@ __global__ void k_sum_partials(const double *__restrict__ p, int n, double *out)
 // k of canonical row r goes to the slot of its rank among the row's internal
 // column ids; slots past the row's size hold the row itself with weight 0;
 // rows past N_int (tail of the last slice) hold column 0 with weight 0.
-__global__ void k_pack_ell(int64_t N_int, int32_t n_max, int32_t kmax, int64_t nslices, int layout,
+// The packed rows are internal rows row0 .. row0 + nrows - 1.  With
+// zero_self, a row's own entry keeps its slot with weight 0 and its weight is
+// written to wself[i] instead (the Neumann rows, solved for their own value).
+__global__ void k_pack_ell(int64_t row0, int64_t nrows, int32_t n_max, int32_t kmax, int64_t nslices, int layout,
                            const int32_t *__restrict__ perm, const int32_t *__restrict__ iperm,
                            const int32_t *__restrict__ sten, const int16_t *__restrict__ nrow,
                            const double *__restrict__ w_can, const int64_t *__restrict__ slice_ptr,
                            const int32_t *__restrict__ slice_len, int32_t *__restrict__ idx, double *__restrict__ w,
-                           float *__restrict__ w32) {
+                           float *__restrict__ w32, double *__restrict__ wself) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = t / kmax;
     const int k = (int)(t - i * kmax);
@@ -408,14 +411,15 @@ __global__ void k_pack_ell(int64_t N_int, int32_t n_max, int32_t kmax, int64_t n
     const int len = slice_len[s];
     if (k >= len) return;
     const int64_t base = slice_ptr[s];
+    const int64_t gi = row0 + i;
     int32_t col = 0;
     double wk = 0.0;
     int slot = k;
-    if (i < N_int) {
-        const int64_t r = perm[i];
+    if (i < nrows) {
+        const int64_t r = perm[gi];
         const int n = nrow[r];
         if (k >= n) {
-            col = (int32_t)i;
+            col = (int32_t)gi;
         } else {
             const int32_t *row = sten + r * (int64_t)n_max;
             col = iperm[row[k]];
@@ -423,12 +427,43 @@ __global__ void k_pack_ell(int64_t N_int, int32_t n_max, int32_t kmax, int64_t n
             for (int q = 0; q < n; ++q) rank += (iperm[row[q]] < col) ? 1 : 0;
             slot = rank;
             wk = w_can[r * (int64_t)n_max + k];
+            if (wself && col == gi) {
+                wself[i] = wk;
+                wk = 0.0;
+            }
         }
     }
     const int64_t pos = ell_pos(layout, base, slot, lane);
     idx[pos] = col;
     w[pos] = wk;
     if (w32) w32[pos] = (float)wk;
+}
+
+// Neumann update, first half: nb[j] = (g_j - sum_{k != self} w_jk u_k) / w_jj
+// for Neumann row j (internal row N_int + j), all from the current iterate.
+template <int WAVES, int U, int LAYOUT>
+__global__ __launch_bounds__(WAVES * 64) void k_neumann_eval(
+    const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
+    const double *__restrict__ w, int64_t nslices, int64_t N_int, int64_t N_neu, const double *__restrict__ wself,
+    const double *__restrict__ g, const double *__restrict__ u, double *__restrict__ nb) {
+    const int64_t slice = (int64_t)blockIdx.x * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (slice >= nslices) return;
+    const int len = slice_len[slice];
+    const double acc = RowDot<double, U, LAYOUT>::run(idx, w, u, slice_ptr[slice], lane, len);
+    const int64_t j = slice * kSlice + lane;
+    if (j >= N_neu) return;
+    if (g) nb[j] = (g[N_int + j] - acc) / wself[j];
+    else nb[N_int + j] = acc + wself[j] * u[N_int + j];  // without data: the derivative itself
+}
+
+// Neumann update, second half: store the new values in both iterate buffers.
+__global__ void k_neumann_store(int64_t N_int, int64_t N_neu, const double *__restrict__ nb, double *__restrict__ ua,
+                                double *__restrict__ ub) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N_neu) return;
+    ua[N_int + j] = nb[j];
+    ub[N_int + j] = nb[j];
 }
 
 __global__ void k_gather(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ src,
@@ -531,13 +566,44 @@ struct OuterRes {
 
 }  // namespace
 
-hipError_t launch_pack_ell(hipStream_t s, int64_t N_int, int32_t n_max, const int32_t *perm, const int32_t *iperm,
-                           const int32_t *sten, const int16_t *nrow, const double *w_can, const Ell &e) {
+hipError_t launch_pack_ell(hipStream_t s, int64_t row0, int64_t nrows, int32_t n_max, const int32_t *perm,
+                           const int32_t *iperm, const int32_t *sten, const int16_t *nrow, const double *w_can,
+                           const Ell &e, double *wself) {
     const int32_t kmax = e.max_len;
     const int64_t total = e.nslices * kSlice * (int64_t)kmax;
     if (!total) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_ell, dim3(grid1d(total, 256)), dim3(256), 0, s, N_int, n_max, kmax, e.nslices, e.layout,
-                       perm, iperm, sten, nrow, w_can, e.slice_ptr, e.slice_len, e.idx, e.w, e.w32);
+    hipLaunchKernelGGL(k_pack_ell, dim3(grid1d(total, 256)), dim3(256), 0, s, row0, nrows, n_max, kmax, e.nslices,
+                       e.layout, perm, iperm, sten, nrow, w_can, e.slice_ptr, e.slice_len, e.idx, e.w, e.w32, wself);
+    return hipGetLastError();
+}
+
+// The Neumann update of one step (evaluate all new boundary values from the
+// current iterate, then store them in both buffers).
+hipError_t launch_neumann_update(hipStream_t s, const Ell &e, int64_t N_int, int64_t N_neu, const double *wself,
+                                 const double *g, double *u_cur, double *u_next, double *nb) {
+    if (!e.nslices) return hipSuccess;
+    const unsigned grid = grid1d(e.nslices, 4);
+    if (e.layout)
+        hipLaunchKernelGGL((k_neumann_eval<4, 8, 1>), dim3(grid), dim3(256), 0, s, e.slice_ptr, e.slice_len, e.idx,
+                           e.w, e.nslices, N_int, N_neu, wself, g, u_cur, nb);
+    else
+        hipLaunchKernelGGL((k_neumann_eval<4, 8, 0>), dim3(grid), dim3(256), 0, s, e.slice_ptr, e.slice_len, e.idx,
+                           e.w, e.nslices, N_int, N_neu, wself, g, u_cur, nb);
+    hipLaunchKernelGGL(k_neumann_store, dim3(grid1d(N_neu, 256)), dim3(256), 0, s, N_int, N_neu, nb, u_cur, u_next);
+    return hipGetLastError();
+}
+
+// out[N_int + j] = (D u) at Neumann row j (its normal-derivative stencil).
+hipError_t launch_neumann_apply(hipStream_t s, const Ell &e, int64_t N_int, int64_t N_neu, const double *wself,
+                                const double *u, double *out) {
+    if (!e.nslices) return hipSuccess;
+    const unsigned grid = grid1d(e.nslices, 4);
+    if (e.layout)
+        hipLaunchKernelGGL((k_neumann_eval<4, 8, 1>), dim3(grid), dim3(256), 0, s, e.slice_ptr, e.slice_len, e.idx,
+                           e.w, e.nslices, N_int, N_neu, wself, nullptr, u, out);
+    else
+        hipLaunchKernelGGL((k_neumann_eval<4, 8, 0>), dim3(grid), dim3(256), 0, s, e.slice_ptr, e.slice_len, e.idx,
+                           e.w, e.nslices, N_int, N_neu, wself, nullptr, u, out);
     return hipGetLastError();
 }
 

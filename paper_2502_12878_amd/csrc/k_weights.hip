@@ -48,6 +48,8 @@ struct WCtx {
     const int32_t *rows;    // centre ids, grouped by (n, m)
     const int8_t *mrow;     // m per listed centre
     double *w_out;          // [N][n_max] canonical
+    const int8_t *type;     // node types (2 = Neumann: normal-derivative row)
+    const double *normals;  // [dim][N] unit normals of Neumann nodes (or null)
     double *scratch;        // LARGE slabs
     int64_t slab;           // doubles per slab
     int panel;
@@ -96,8 +98,11 @@ __device__ void report_status(DevStatus *st, int code, int64_t node) {
 }
 
 // Element (k, l) of the augmented matrix, 0 <= l <= S (column S = rhs).
+// op 0: Laplacian rows; op 1: derivative along the unit normal nv (Neumann
+// rows), whose right-hand side is 3|y_k| ((0 - y_k) . nv) for the r^3 block
+// and nv_a for the linear monomial y_a.
 __device__ __forceinline__ double entry(int k, int l, int n, int M, int S, int dim, const double *y,
-                                        const int8_t *ex) {
+                                        const int8_t *ex, int op, const double *nv) {
     const double c3 = 3.0 * (double)(dim + 1);
     if (l == S) {
         if (k < n) {
@@ -106,12 +111,25 @@ __device__ __forceinline__ double entry(int k, int l, int n, int M, int S, int d
                 const double t2 = y[3 * k + a] * y[3 * k + a];
                 r2 = (a == 0) ? t2 : r2 + t2;
             }
-            return c3 * sqrt(r2);
+            if (op == 0) return c3 * sqrt(r2);
+            double dn = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                const double t = (0.0 - y[3 * k + a]) * nv[a];
+                dn = (a == 0) ? t : dn + t;
+            }
+            return (3.0 * sqrt(r2)) * dn;
         }
         const int j = k - n;
         const int deg = ex[3 * j] + ex[3 * j + 1] + ex[3 * j + 2];
-        const bool pure = ex[3 * j] == 2 || ex[3 * j + 1] == 2 || ex[3 * j + 2] == 2;
-        return (deg == 2 && pure) ? 2.0 : 0.0;
+        if (op == 0) {
+            const bool pure = ex[3 * j] == 2 || ex[3 * j + 1] == 2 || ex[3 * j + 2] == 2;
+            return (deg == 2 && pure) ? 2.0 : 0.0;
+        }
+        double v = 0.0;
+        if (deg == 1)
+            for (int a = 0; a < dim; ++a)
+                if (ex[3 * j + a] == 1) v = nv[a];
+        return v;
     }
     if (k < n && l < n) {
         double r2 = 0.0;
@@ -261,6 +279,10 @@ __device__ void solve_lds_item(const WCtx &cx, const Item &it, char *lds, int S_
     const int m = cx.mrow[li];
     const int M = num_monomials(cx.dim, m);
     const int S = n + M;  // uniform over the item
+    const int op = cx.type[c] == 2 ? 1 : 0;
+    double nv[3] = {0.0, 0.0, 0.0};
+    if (op)
+        for (int a = 0; a < cx.dim; ++a) nv[a] = cx.normals[a * cx.N + c];
     if (t == 0) make_exponents(cx.dim, m, ex);
     local_coords(cx, c, n, y, &gs->s, t, T, red);
     __syncthreads();
@@ -268,7 +290,7 @@ __device__ void solve_lds_item(const WCtx &cx, const Item &it, char *lds, int S_
     double amax = 0.0;
     for (int q = t; q < S * C; q += T) {
         const int k = q / C, l = q % C;
-        const double v = entry(k, l, n, M, S, cx.dim, y, ex);
+        const double v = entry(k, l, n, M, S, cx.dim, y, ex, op, nv);
         A[k * ld + l] = v;
         if (l < S) amax = fmax(amax, fabs(v));
     }
@@ -287,7 +309,7 @@ __device__ void solve_lds_item(const WCtx &cx, const Item &it, char *lds, int S_
     double *w = cx.w_out + c * (int64_t)cx.n_max;
     if (active) {
         if (ok) {
-            const double s2 = s * s;
+            const double s2 = op ? s : s * s;  // degree -2 (Laplacian) or -1 (derivative)
             for (int k = t; k < n; k += T) w[k] = xs[k] / s2;
         } else {
             for (int k = t; k < n; k += T) w[k] = 0.0;
@@ -322,6 +344,10 @@ __device__ void solve_blocked_item(const WCtx &cx, const Item &it, char *lds) {
     int8_t *ex = (int8_t *)(pivs + 64);
     GroupScratch *gs = (GroupScratch *)(((uintptr_t)(ex + 84 * 3) + 15) & ~(uintptr_t)15);
 
+    const int op = cx.type[c] == 2 ? 1 : 0;
+    double nv[3] = {0.0, 0.0, 0.0};
+    if (op)
+        for (int a = 0; a < cx.dim; ++a) nv[a] = cx.normals[a * cx.N + c];
     if (t == 0) make_exponents(cx.dim, m, ex);
     local_coords(cx, c, n, y, &gs->s, t, kBS, red);
     __syncthreads();
@@ -329,7 +355,7 @@ __device__ void solve_blocked_item(const WCtx &cx, const Item &it, char *lds) {
     double amax = 0.0;
     for (int64_t q = t; q < (int64_t)S * C; q += kBS) {
         const int k = (int)(q / C), l = (int)(q % C);
-        const double v = entry(k, l, n, M, S, cx.dim, y, ex);
+        const double v = entry(k, l, n, M, S, cx.dim, y, ex, op, nv);
         A[(int64_t)k * ld + l] = v;
         if (l < S) amax = fmax(amax, fabs(v));
     }
@@ -501,7 +527,7 @@ __device__ void solve_blocked_item(const WCtx &cx, const Item &it, char *lds) {
         }
         __syncthreads();
     }
-    const double s2 = s * s;
+    const double s2 = op ? s : s * s;  // degree -2 (Laplacian) or -1 (derivative)
     for (int k = t; k < n; k += kBS) w[k] = bx[k] / s2;
     __syncthreads();
 }
@@ -564,10 +590,11 @@ int weights_grid(int S_small, int S_mid, int S_large, int panel) {
 // The host builds the queue (largest first) and sizes LDS for what is present.
 hipError_t launch_weights_items(hipStream_t s, int dim, int64_t N, const double *xyz, const int32_t *sten,
                                 const int16_t *nrow, int32_t n_max, const int32_t *rows, const int8_t *mrow,
-                                double *w_out, double *scratch, int64_t slab, int panel, DevStatus *status,
-                                const void *items, int64_t nitems, int32_t *counter, int S_small, int S_mid,
-                                int S_large, int grid, int nslabs, size_t *lds_used) {
-    WCtx cx{dim, N, xyz, sten, nrow, n_max, rows, mrow, w_out, scratch, slab, panel, status};
+                                const int8_t *type, const double *normals, double *w_out, double *scratch,
+                                int64_t slab, int panel, DevStatus *status, const void *items, int64_t nitems,
+                                int32_t *counter, int S_small, int S_mid, int S_large, int grid, int nslabs,
+                                size_t *lds_used) {
+    WCtx cx{dim, N, xyz, sten, nrow, n_max, rows, mrow, w_out, type, normals, scratch, slab, panel, status};
     const size_t lds = lds_total(S_small, S_mid, S_large, panel);
     if (lds_used) *lds_used = lds;
     if (grid <= 0) return hipErrorInvalidConfiguration;

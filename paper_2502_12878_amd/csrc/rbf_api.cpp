@@ -115,6 +115,13 @@ void drop_operator(rbf_handle *h) {
     free_t(h, h->ellT.idx);
     free_t(h, h->ellT.w);
     h->ellT = Ell{};
+    free_t(h, h->ellN.slice_ptr);
+    free_t(h, h->ellN.slice_len);
+    free_t(h, h->ellN.idx);
+    free_t(h, h->ellN.w);
+    h->ellN = Ell{};
+    free_t(h, h->wself);
+    free_t(h, h->nb);
     free_t(h, h->ua);
     free_t(h, h->ub);
     free_t(h, h->fint);
@@ -372,11 +379,14 @@ rbf_status rbf_set_nodes(rbf_handle *h, int dim, int64_t N, const double *xyz_de
     std::vector<int8_t> th((size_t)N);
     HIPCHK(h, hipMemcpyAsync(th.data(), type_dev, (size_t)N, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    int64_t nint = 0;
+    int64_t nint = 0, nneu = 0;
     for (int64_t i = 0; i < N; ++i) {
-        if (th[i] != 0 && th[i] != 1) return fail(h, RBF_EINVAL, "node %" PRId64 " has type %d (must be 0 or 1)", i, (int)th[i]);
+        if (th[i] < 0 || th[i] > 2)
+            return fail(h, RBF_EINVAL, "node %" PRId64 " has type %d (must be 0, 1 or 2)", i, (int)th[i]);
         nint += th[i] == 0;
+        nneu += th[i] == 2;
     }
+    free_t(h, h->normals);
     ALLOC(h, h->xyz, double, (size_t)dim * N);
     ALLOC(h, h->type, int8_t, N);
     HIPCHK(h, hipMemcpyAsync(h->xyz, xyz_dev, sizeof(double) * dim * N, hipMemcpyDeviceToDevice, h->stream));
@@ -385,7 +395,33 @@ rbf_status rbf_set_nodes(rbf_handle *h, int dim, int64_t N, const double *xyz_de
     h->dim = dim;
     h->N = N;
     h->N_int = nint;
+    h->N_neu = nneu;
     h->type_h.swap(th);
+    return RBF_OK;
+}
+
+rbf_status rbf_set_normals(rbf_handle *h, const double *normals_dev) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (h->N == 0) return fail(h, RBF_EINVAL, "no nodes set");
+    if (!normals_dev) return fail(h, RBF_EINVAL, "null normals");
+    DeviceGuard g(h->device);
+    const int64_t N = h->N;
+    const int dim = h->dim;
+    std::vector<double> nh((size_t)dim * N);
+    HIPCHK(h, hipMemcpyAsync(nh.data(), normals_dev, sizeof(double) * dim * N, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int64_t i = 0; i < N; ++i) {
+        if (h->type_h[i] != 2) continue;
+        double s2 = 0.0;
+        for (int a = 0; a < dim; ++a) s2 += nh[a * N + i] * nh[a * N + i];
+        if (!(std::fabs(s2 - 1.0) <= 1e-12)) return fail(h, RBF_EINVAL, "Neumann node %" PRId64 ": normal is not a unit vector", i);
+    }
+    drop_weights(h);
+    free_t(h, h->normals);
+    ALLOC(h, h->normals, double, (size_t)dim * N);
+    HIPCHK(h, hipMemcpyAsync(h->normals, normals_dev, sizeof(double) * dim * N, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
     return RBF_OK;
 }
 
@@ -413,6 +449,9 @@ rbf_status rbf_build_stencils(rbf_handle *h, int32_t n_uniform, const int16_t *n
             n_max = std::max<int32_t>(n_max, nh[i]);
         }
     }
+    // a Neumann node draws its support from itself and the interior nodes
+    if (h->N_neu > 0 && n_max > h->N_int + 1)
+        return fail(h, RBF_EINVAL, "Neumann supports of %d nodes need at least %d interior nodes", n_max, n_max - 1);
     drop_stencils(h);
 
     // bounding box
@@ -490,7 +529,7 @@ rbf_status rbf_build_stencils(rbf_handle *h, int32_t n_uniform, const int16_t *n
     rbf_status st = reset_status(h);
     if (st) return st;
     HIPCHK(h, launch_knn_query(h->stream, cg, N, h->xyz, xyz_c, cell_of, start, ids, n_uniform, n_per_node_dev,
-                               n_max, ball_coef, margin, h->sten, h->nrow, h->dstatus));
+                               n_max, ball_coef, margin, h->sten, h->nrow, h->type, h->dstatus));
     DevStatus ds;
     st = read_status(h, &ds);
     dfree(h, cell_of);
@@ -514,42 +553,21 @@ rbf_status rbf_build_stencils(rbf_handle *h, int32_t n_uniform, const int16_t *n
 }
 
 // ====================================================================== packed operator
-// Internal order: interior rows by descending support size then canonical id,
-// then Dirichlet rows by canonical id.
-static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
-    drop_operator(h);
-    const int64_t N = h->N, N_int = h->N_int;
-    std::vector<int32_t> perm((size_t)N), iperm((size_t)N);
-    {
-        std::vector<int64_t> cnt(kMaxSupport + 2, 0);
-        for (int64_t i = 0; i < N; ++i)
-            if (h->type_h[i] == 0) cnt[h->nrow_h[i]]++;
-        std::vector<int64_t> off(kMaxSupport + 2, 0);
-        int64_t acc = 0;
-        for (int n = kMaxSupport; n >= 1; --n) {
-            off[n] = acc;
-            acc += cnt[n];
-        }
-        int64_t bpos = N_int;
-        for (int64_t i = 0; i < N; ++i) {
-            if (h->type_h[i] == 0) perm[off[h->nrow_h[i]]++] = (int32_t)i;
-            else perm[bpos++] = (int32_t)i;
-        }
-        for (int64_t k = 0; k < N; ++k) iperm[perm[k]] = (int32_t)k;
-    }
+// Sliced operator over internal rows [row0, row0 + nrows) (perm gives their
+// canonical ids); with wself, each row's own weight is split out (Neumann rows).
+static rbf_status make_ell(rbf_handle *h, int64_t row0, int64_t nrows, const std::vector<int32_t> &perm, int layout,
+                           int keep_fp32, Ell *out, double *wself) {
     Ell e;
-    // packed layout: entry pairs as vectors unless RBF_ELL_LAYOUT=0
-    const char *lay = std::getenv("RBF_ELL_LAYOUT");
-    e.layout = (lay && lay[0] == '0') ? 0 : 1;
-    e.nslices = (N_int + kSlice - 1) / kSlice;
+    e.layout = layout;
+    e.nslices = (nrows + kSlice - 1) / kSlice;
     std::vector<int64_t> sptr((size_t)e.nslices + 1);
     std::vector<int32_t> slen((size_t)e.nslices);
     int64_t acc = 0;
     int32_t mx = 0;
     for (int64_t s = 0; s < e.nslices; ++s) {
         int32_t len = 0;
-        for (int64_t i = s * kSlice; i < std::min<int64_t>(N_int, (s + 1) * kSlice); ++i)
-            len = std::max<int32_t>(len, h->nrow_h[perm[i]]);
+        for (int64_t i = s * kSlice; i < std::min<int64_t>(nrows, (s + 1) * kSlice); ++i)
+            len = std::max<int32_t>(len, h->nrow_h[perm[row0 + i]]);
         if (e.layout == 1) len += len & 1;
         slen[s] = len;
         sptr[s] = acc;
@@ -559,21 +577,73 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
     sptr[e.nslices] = acc;
     e.elems = acc;
     e.max_len = mx;
-    ALLOC(h, h->perm, int32_t, N);
-    ALLOC(h, h->iperm, int32_t, N);
     ALLOC(h, e.slice_ptr, int64_t, e.nslices + 1);
     ALLOC(h, e.slice_len, int32_t, std::max<int64_t>(1, e.nslices));
     ALLOC(h, e.idx, int32_t, std::max<int64_t>(1, e.elems));
     ALLOC(h, e.w, double, std::max<int64_t>(1, e.elems));
     if (keep_fp32) ALLOC(h, e.w32, float, std::max<int64_t>(1, e.elems));
-    h->ell = e;
+    *out = e;
+    HIPCHK(h, hipMemcpyAsync(e.slice_ptr, sptr.data(), sizeof(int64_t) * (e.nslices + 1), hipMemcpyHostToDevice, h->stream));
+    if (e.nslices) {
+        HIPCHK(h, hipMemcpyAsync(e.slice_len, slen.data(), sizeof(int32_t) * e.nslices, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, launch_pack_ell(h->stream, row0, nrows, h->n_max, h->perm, h->iperm, h->sten, h->nrow, h->w_can, e,
+                                  wself));
+    }
+    return RBF_OK;
+}
+
+// Internal order: interior rows by descending support size then canonical id,
+// then Neumann rows likewise, then Dirichlet rows by canonical id.
+static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
+    drop_operator(h);
+    const int64_t N = h->N, N_int = h->N_int, N_neu = h->N_neu;
+    std::vector<int32_t> perm((size_t)N), iperm((size_t)N);
+    {
+        std::vector<int64_t> cnt(2 * (kMaxSupport + 2), 0);
+        for (int64_t i = 0; i < N; ++i)
+            if (h->type_h[i] != 1) cnt[(h->type_h[i] == 2) * (kMaxSupport + 2) + h->nrow_h[i]]++;
+        std::vector<int64_t> off(2 * (kMaxSupport + 2), 0);
+        int64_t acc = 0;
+        for (int g = 0; g < 2; ++g)
+            for (int n = kMaxSupport; n >= 1; --n) {
+                off[g * (kMaxSupport + 2) + n] = acc;
+                acc += cnt[g * (kMaxSupport + 2) + n];
+            }
+        int64_t bpos = N_int + N_neu;
+        for (int64_t i = 0; i < N; ++i) {
+            if (h->type_h[i] == 1) perm[bpos++] = (int32_t)i;
+            else perm[off[(h->type_h[i] == 2) * (kMaxSupport + 2) + h->nrow_h[i]]++] = (int32_t)i;
+        }
+        for (int64_t k = 0; k < N; ++k) iperm[perm[k]] = (int32_t)k;
+    }
+    ALLOC(h, h->perm, int32_t, N);
+    ALLOC(h, h->iperm, int32_t, N);
     HIPCHK(h, hipMemcpyAsync(h->perm, perm.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->iperm, iperm.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(e.slice_ptr, sptr.data(), sizeof(int64_t) * (e.nslices + 1), hipMemcpyHostToDevice, h->stream));
-    if (e.nslices)
-        HIPCHK(h, hipMemcpyAsync(e.slice_len, slen.data(), sizeof(int32_t) * e.nslices, hipMemcpyHostToDevice, h->stream));
-    if (e.nslices)
-        HIPCHK(h, launch_pack_ell(h->stream, N_int, h->n_max, h->perm, h->iperm, h->sten, h->nrow, h->w_can, h->ell));
+    // packed layout: entry pairs as vectors unless RBF_ELL_LAYOUT=0
+    const char *lay = std::getenv("RBF_ELL_LAYOUT");
+    const int layout = (lay && lay[0] == '0') ? 0 : 1;
+    rbf_status st = make_ell(h, 0, N_int, perm, layout, keep_fp32, &h->ell, nullptr);
+    if (st) return st;
+    Ell &e = h->ell;
+    if (N_neu > 0) {
+        ALLOC(h, h->wself, double, N_neu);
+        ALLOC(h, h->nb, double, N_neu);
+        HIPCHK(h, launch_fill_f64(h->stream, N_neu, 0.0, h->wself));
+        st = make_ell(h, N_int, N_neu, perm, layout, 0, &h->ellN, h->wself);
+        if (st) return st;
+        // each Neumann row divides by its own weight: it must be present and nonzero
+        std::vector<double> ws((size_t)N_neu);
+        HIPCHK(h, hipMemcpyAsync(ws.data(), h->wself, sizeof(double) * N_neu, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        for (int64_t j = 0; j < N_neu; ++j)
+            if (!(std::fabs(ws[j]) > 0.0) || !std::isfinite(ws[j])) {
+                const int64_t r = perm[N_int + j];
+                drop_operator(h);
+                h->have_w = false;
+                return fail(h, RBF_EINVAL, "Neumann node %" PRId64 ": own weight missing, zero or not finite", r);
+            }
+    }
     ALLOC(h, h->ua, double, N);
     ALLOC(h, h->ub, double, N);
     ALLOC(h, h->fint, double, N);
@@ -624,14 +694,15 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
         HIPCHK(h, hipStreamSynchronize(h->stream));
     }
     for (int64_t i = 0; i < N; ++i)
-        if (h->type_h[i] == 0 && (mh[i] < 0 || mh[i] > kMaxOrder))
+        if (h->type_h[i] != 1 && (mh[i] < 0 || mh[i] > kMaxOrder))
             return fail(h, RBF_EINVAL, "node %" PRId64 ": order %d not in 0..%d", i, (int)mh[i], kMaxOrder);
+    if (h->N_neu > 0 && !h->normals) return fail(h, RBF_EINVAL, "Neumann nodes need normals (rbf_set_normals)");
     drop_weights(h);
 
     // group interior rows by (n, m); classes by descending system size
     std::map<std::pair<int, int>, std::vector<int32_t>> cls;
     for (int64_t i = 0; i < N; ++i)
-        if (h->type_h[i] == 0) cls[{h->nrow_h[i], mh[i]}].push_back((int32_t)i);
+        if (h->type_h[i] != 1) cls[{h->nrow_h[i], mh[i]}].push_back((int32_t)i);
     struct Cls { int S, n, m; std::vector<int32_t> *rows; };
     std::vector<Cls> order;
     for (auto &kv : cls) order.push_back({kv.first.first + num_monomials(dim, kv.first.second), kv.first.first, kv.first.second, &kv.second});
@@ -702,7 +773,8 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
                     HIPCHK(h, hipMemsetAsync(counter, 0, sizeof(int32_t), h->stream));
                     HIPCHK(h, hipEventRecord(h->ev0, h->stream));
                     HIPCHK(h, launch_weights_items(h->stream, dim, N, h->xyz, h->sten, h->nrow, h->n_max, d_rows, d_m,
-                                                   h->w_can, scratch, slab, pc, h->dstatus, d_items, sample, counter,
+                                                   h->type, h->normals, h->w_can, scratch, slab, pc, h->dstatus,
+                                                   d_items, sample, counter,
                                                    0, 0, S_large, weights_grid(0, 0, S_large, pc), grid_max,
                                                    nullptr));
                     HIPCHK(h, hipEventRecord(h->ev1, h->stream));
@@ -722,8 +794,9 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
         rbf_status st = reset_status(h);
         if (st) return st;
         HIPCHK(h, hipMemsetAsync(counter, 0, sizeof(int32_t), h->stream));
-        HIPCHK(h, launch_weights_items(h->stream, dim, N, h->xyz, h->sten, h->nrow, h->n_max, d_rows, d_m, h->w_can,
-                                       scratch, slab, panel, h->dstatus, d_items, nitems, counter, S_small, S_mid,
+        HIPCHK(h, launch_weights_items(h->stream, dim, N, h->xyz, h->sten, h->nrow, h->n_max, d_rows, d_m, h->type,
+                                       h->normals, h->w_can, scratch, slab, panel, h->dstatus, d_items, nitems,
+                                       counter, S_small, S_mid,
                                        S_large, weights_grid(S_small, S_mid, S_large, panel), grid_max, nullptr));
         DevStatus ds;
         st = read_status(h, &ds);
@@ -768,6 +841,7 @@ extern "C" rbf_status rbf_set_stencils(rbf_handle *h, const int32_t *idx_host, i
     if (!idx_host || n_max < 1 || n_max > kMaxSupport) return fail(h, RBF_EINVAL, "bad stencil array or n_max");
     const int64_t N = h->N;
     std::vector<int16_t> nr((size_t)N);
+    std::vector<int32_t> row;
     for (int64_t r = 0; r < N; ++r) {
         int n = 0;
         while (n < n_max && idx_host[r * n_max + n] >= 0) ++n;
@@ -777,6 +851,11 @@ extern "C" rbf_status rbf_set_stencils(rbf_handle *h, const int32_t *idx_host, i
             if (k < n && v >= N) return fail(h, RBF_EINVAL, "row %" PRId64 ": id %d out of range", r, v);
             if (k >= n && v != -1) return fail(h, RBF_EINVAL, "row %" PRId64 ": padding must be -1", r);
         }
+        // the packed layout places each entry by its rank among the row's ids
+        row.assign(idx_host + r * n_max, idx_host + r * n_max + n);
+        std::sort(row.begin(), row.end());
+        if (std::adjacent_find(row.begin(), row.end()) != row.end())
+            return fail(h, RBF_EINVAL, "row %" PRId64 ": repeated node id in the stencil", r);
         nr[r] = (int16_t)n;
     }
     DeviceGuard g(h->device);
@@ -801,7 +880,7 @@ extern "C" rbf_status rbf_set_weights(rbf_handle *h, const double *w_host, int k
     std::vector<double> w((size_t)N * nm);
     for (int64_t r = 0; r < N; ++r)
         for (int64_t k = 0; k < nm; ++k) {
-            const bool live = h->type_h[r] == 0 && k < h->nrow_h[r];
+            const bool live = h->type_h[r] != 1 && k < h->nrow_h[r];
             w[r * nm + k] = live ? w_host[r * nm + k] : 0.0;
         }
     DeviceGuard g(h->device);
@@ -824,6 +903,7 @@ extern "C" rbf_status rbf_apply(rbf_handle *h, const double *u_dev, double *Lu_d
     HIPCHK(h, launch_gather(h->stream, N, h->perm, u_dev, h->ua));
     HIPCHK(h, launch_fill_f64(h->stream, N - Ni, 0.0, h->tmp + Ni));
     if (Ni) HIPCHK(h, launch_apply_f64(h->stream, h->cfg, h->ell, Ni, h->ua, h->tmp, nullptr, nullptr));
+    if (h->N_neu) HIPCHK(h, launch_neumann_apply(h->stream, h->ellN, Ni, h->N_neu, h->wself, h->ua, h->tmp));
     HIPCHK(h, launch_scatter(h->stream, N, h->perm, h->tmp, Lu_dev));
     return RBF_OK;
 }
@@ -957,7 +1037,10 @@ static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, d
         double *a = start ? h->ub : h->ua, *b = start ? h->ua : h->ub;
         for (int64_t i = 0; i < steps && e == hipSuccess; ++i) {
             const bool report = kind == kGraphF64 && i == steps - 1;
-            e = launch_sweep_f64(s, h->cfg, h->ell, Ni, h->fint, a, b, dt, report ? h->dslots : nullptr);
+            // Neumann rows first take their values from the current iterate
+            if (h->N_neu > 0) e = launch_neumann_update(s, h->ellN, Ni, h->N_neu, h->wself, h->fint, a, b, h->nb);
+            if (e == hipSuccess)
+                e = launch_sweep_f64(s, h->cfg, h->ell, Ni, h->fint, a, b, dt, report ? h->dslots : nullptr);
             std::swap(a, b);
         }
     } else if (kind == kGraphMixed) {
@@ -1019,6 +1102,8 @@ extern "C" rbf_status rbf_iterate(rbf_handle *h, const double *f_dev, double *u_
     if (p->mode != RBF_MODE_FP64 && p->mode != RBF_MODE_MIXED) return fail(h, RBF_EINVAL, "unknown mode %d", p->mode);
     if (p->mode == RBF_MODE_MIXED && (p->inner_steps < 1 || !h->have_w32))
         return fail(h, RBF_EINVAL, "mixed mode needs inner_steps >= 1 and FP32 weights (keep_fp32)");
+    if (p->mode == RBF_MODE_MIXED && h->N_neu > 0)
+        return fail(h, RBF_EINVAL, "mixed precision is implemented for Dirichlet problems only");
     if (p->stall_chunks < 0) return fail(h, RBF_EINVAL, "stall_chunks must be >= 0");
     DeviceGuard g(h->device);
     std::memset(rep, 0, sizeof *rep);
@@ -1232,6 +1317,7 @@ extern "C" rbf_status rbf_adjoint_f(rbf_handle *h, const double *gK_dev, int64_t
     h->err.clear();
     if (!h->have_w || !h->ua) return fail(h, RBF_EINVAL, "no operator");
     if (!gK_dev || !grad_f_dev) return fail(h, RBF_EINVAL, "null pointer");
+    if (h->N_neu > 0) return fail(h, RBF_EINVAL, "the adjoint is implemented for Dirichlet problems only");
     if (K < 1 || every < 1 || every > K || K % every) return fail(h, RBF_EINVAL, "need 1 <= every <= K, K %% every == 0");
     if (!std::isfinite(dt)) return fail(h, RBF_EINVAL, "dt must be finite");
     DeviceGuard g(h->device);

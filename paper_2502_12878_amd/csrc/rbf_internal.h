@@ -77,9 +77,10 @@ struct rbf_handle {
 
     // nodes (canonical order)
     int dim = 0;
-    int64_t N = 0, N_int = 0;
-    double *xyz = nullptr;   // [dim][N]
-    int8_t *type = nullptr;  // [N]
+    int64_t N = 0, N_int = 0, N_neu = 0;
+    double *xyz = nullptr;      // [dim][N]
+    int8_t *type = nullptr;     // [N]: 0 interior, 1 Dirichlet, 2 Neumann
+    double *normals = nullptr;  // [dim][N] unit outward normals (Neumann nodes)
 
     // stencils and weights (canonical order, row-major [N][n_max])
     int32_t n_max = 0;
@@ -93,6 +94,9 @@ struct rbf_handle {
     int32_t *iperm = nullptr;  // canonical -> internal
     rbf::Ell ell;
     rbf::Ell ellT;             // transposed interior operator (built on first use)
+    rbf::Ell ellN;             // Neumann rows (internal N_int ..), own entry zeroed
+    double *wself = nullptr;   // [N_neu] own weight of each Neumann row
+    double *nb = nullptr;      // [N_neu] new Neumann values of a step
 
     // iteration vectors (internal order)
     double *ua = nullptr, *ub = nullptr, *fint = nullptr, *tmp = nullptr, *uref = nullptr;
@@ -142,7 +146,8 @@ hipError_t launch_coords_by_cell(hipStream_t s, int dim, int64_t N, const double
 hipError_t launch_knn_query(hipStream_t s, const CellGrid &g, int64_t N, const double *xyz, const double *xyz_c,
                             const int32_t *cell_of, const int32_t *cell_start, const int32_t *ids_by_cell,
                             int32_t n_uniform, const int16_t *n_per_node, int32_t n_max, double ball_coef,
-                            double margin, int32_t *sten, int16_t *nrow_out, DevStatus *status);
+                            double margin, int32_t *sten, int16_t *nrow_out, const int8_t *type,
+                            DevStatus *status);
 
 // ---------------------------------------------------------------- weights
 int weights_small_limit();
@@ -152,13 +157,19 @@ size_t weights_item_bytes();
 void weights_make_item(void *dst, int kind, int count, int64_t first);
 hipError_t launch_weights_items(hipStream_t s, int dim, int64_t N, const double *xyz, const int32_t *sten,
                                 const int16_t *nrow, int32_t n_max, const int32_t *rows, const int8_t *mrow,
-                                double *w_out, double *scratch, int64_t slab, int panel, DevStatus *status,
-                                const void *items, int64_t nitems, int32_t *counter, int S_small, int S_mid,
-                                int S_large, int grid, int nslabs, size_t *lds_used);
+                                const int8_t *type, const double *normals, double *w_out, double *scratch,
+                                int64_t slab, int panel, DevStatus *status, const void *items, int64_t nitems,
+                                int32_t *counter, int S_small, int S_mid, int S_large, int grid, int nslabs,
+                                size_t *lds_used);
 
 // ---------------------------------------------------------------- sweep family
-hipError_t launch_pack_ell(hipStream_t s, int64_t N_int, int32_t n_max, const int32_t *perm, const int32_t *iperm,
-                           const int32_t *sten, const int16_t *nrow, const double *w_can, const Ell &e);
+hipError_t launch_pack_ell(hipStream_t s, int64_t row0, int64_t nrows, int32_t n_max, const int32_t *perm,
+                           const int32_t *iperm, const int32_t *sten, const int16_t *nrow, const double *w_can,
+                           const Ell &e, double *wself);
+hipError_t launch_neumann_update(hipStream_t s, const Ell &e, int64_t N_int, int64_t N_neu, const double *wself,
+                                 const double *g, double *u_cur, double *u_next, double *nb);
+hipError_t launch_neumann_apply(hipStream_t s, const Ell &e, int64_t N_int, int64_t N_neu, const double *wself,
+                                const double *u, double *out);
 hipError_t launch_sweep_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
                             const double *u_old, double *u_new, double dt, unsigned long long *res_slot);
 hipError_t launch_sweep_f32(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const float *r,
