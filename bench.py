@@ -363,6 +363,152 @@ def run_support_sweep(m=2, sizes=(20, 30, 40, 60, 80, 100, 130, 168), steps=1000
             "fit_ms_per_byte_per_row": a, "fit_ms_offset": b}
 
 
+def _converge(p, fd, u, dt, uref, tol_rel, max_steps, chunk=500, stall=10):
+    """Iterate to relative residual `tol_rel` (or a 10-chunk stall at the
+    rounding floor); returns the report with the final errors."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, rep = p.iterate(fd, u, dt, max_steps, tol_rel, chunk, stall_chunks=stall, u_ref=uref)
+    torch.cuda.synchronize()
+    rep["wall_s"] = time.perf_counter() - t0
+    rep["status"] = st
+    return rep
+
+
+def run_order_scan(orders=(2, 4, 6), sides=(21, 31, 46, 68, 100), alpha=0.15, tol_rel=1e-11, seed=1):
+    """Augmentation order x node spacing (the paper's time/error scan, Sec.
+    III-B): for each (m, h) on the 3D jittered cube, the wall time per step
+    t_ws, the derived t_T / T = t_ws / (alpha dt_max) with dt_max = h^2/(2d),
+    the steps and wall time to converge, and the error of the converged
+    solution against the exact one (mean |u - u_a| over all nodes as in the
+    paper, and L-inf)."""
+    import numpy as np
+
+    import rbf_inputs as ri
+    from paper_2502_12878_amd import Problem
+    rows = []
+    for m in orders:
+        n = 2 * ri.num_monomials(3, m)
+        for side in sides:
+            h = ri.grid_spacing(side)
+            dt_max = h * h / 6
+            dt = alpha * dt_max
+            xyz_h, typ_h = ri.jittered_grid(3, side, 0.3, seed)
+            u_ex, f, g, u0 = ri.manufactured(3, xyz_h, typ_h)
+            nint = int((typ_h == 0).sum())
+            p = Problem(0)
+            xd, td = p.build_nodes(3, side, 0.3, seed)
+            p.set_nodes(xd, td)
+            del xd, td
+            t0 = time.perf_counter()
+            p.build_stencils(n)
+            p.compute_weights(m)
+            setup = time.perf_counter() - t0
+            if nint >= 200_000:
+                p.autotune()
+            fd, uref = _dev(f), _dev(u_ex)
+            # step time: 2000 steps in graph chunks of 500, after 500 warm-up steps
+            u = _dev(u0)
+            p.iterate(fd, u, dt, 500, 0.0, 500)
+            u = _dev(u0)
+            torch_sync()
+            t1 = time.perf_counter()
+            st, rep = p.iterate(fd, u, dt, 2000, 0.0, 500)
+            torch_sync()
+            t_ws = (time.perf_counter() - t1) / 2000
+            per_sweep, _ = p.last_sweep_time()
+            u = _dev(u0)
+            rc = _converge(p, fd, u, dt, uref, tol_rel, max_steps=int(60.0 / (alpha * h * h)) + 1000)
+            rows.append({"m": m, "n": n, "side": side, "h": h, "interior_nodes": nint, "setup_s": round(setup, 3),
+                         "t_ws_ms": 1e3 * t_ws, "kernel_ms_per_sweep": 1e3 * per_sweep,
+                         "tT_over_T_s": t_ws / (alpha * dt_max), "steps_to_converge": rc["steps"],
+                         "converged": bool(rc["converged"]), "res_final_rel": rc["res_final"] / rc["fnorm"],
+                         "time_to_converge_s": round(rc["wall_s"], 3), "err_mean_abs": rc["err_mean_abs"],
+                         "err_inf": rc["err_inf"]})
+            _progress(f"scan m={m} side={side}: t_ws {1e3 * t_ws:.4f} ms, {rc['steps']} steps, "
+                      f"err_inf {rc['err_inf']:.3e}, mean {rc['err_mean_abs']:.3e}")
+            p.close()
+    slopes = {}
+    for m in orders:
+        r = [x for x in rows if x["m"] == m and x["converged"]]
+        if len(r) >= 3:
+            slopes[str(m)] = round(float(np.polyfit(np.log([x["h"] for x in r]),
+                                                    np.log([x["err_inf"] for x in r]), 1)[0]), 3)
+    return {"workload": f"order x spacing scan: 3D jittered cube (seed {seed}), m in {list(orders)}, "
+                        f"side in {list(sides)}, n = 2M, dt = {alpha}*h^2/6, converged to relative residual "
+                        f"{tol_rel} (or a stall at the rounding floor)",
+            "rows": rows, "err_inf_slope_vs_h": slopes}
+
+
+def run_mixed_bc(side=100, m=4, steps=3000, conv_sides=(21, 31, 46), conv_orders=(2, 4), alpha=0.15, seed=5):
+    """The mixed Dirichlet/Neumann variant on [0, 1/2]^3: sweep throughput with
+    the Neumann update before every step on the side^3 grid, and the error of
+    the converged solution under refinement at small sizes."""
+    import numpy as np
+
+    import rbf_inputs as ri
+    from paper_2502_12878_amd import Problem
+
+    def build(sd, mm):
+        xyz, typ, normals = ri.mixed_bc_grid(3, sd, 0.3, seed)
+        u_ex, f, u0 = ri.manufactured_mixed(3, xyz, typ)
+        p = Problem(0)
+        p.set_nodes(xyz, typ)
+        p.set_normals(normals)
+        t0 = time.perf_counter()
+        p.build_stencils(2 * ri.num_monomials(3, mm))
+        p.compute_weights(mm)
+        return p, typ, u_ex, f, u0, time.perf_counter() - t0
+
+    p, typ, u_ex, f, u0, setup = build(side, m)
+    p.autotune()
+    h = 0.5 / (side - 1)
+    dt = alpha * h * h / 6
+    nint, nneu = int((typ == 0).sum()), int((typ == 2).sum())
+    fd = _dev(f)
+    u = _dev(u0)
+    p.iterate(fd, u, dt, 500, 0.0, 500)
+    u = _dev(u0)
+    torch_sync()
+    t0 = time.perf_counter()
+    st, rep = p.iterate(fd, u, dt, steps, 0.0, 500)
+    torch_sync()
+    wall = time.perf_counter() - t0
+    per_step, nsw = p.last_sweep_time()
+    n = 2 * ri.num_monomials(3, m)
+    p.close()
+    _progress(f"mixed_bc side={side}: {1e3 * per_step:.4f} ms per step (sweep + Neumann update)")
+    conv = []
+    for mm in conv_orders:
+        for sd in conv_sides:
+            q, typ2, ue, f2, u02, _ = build(sd, mm)
+            hh = 0.5 / (sd - 1)
+            rc = _converge(q, _dev(f2), _dev(u02), alpha * hh * hh / 6, _dev(ue), 1e-11,
+                           max_steps=int(30.0 / (alpha * hh * hh)) + 1000)
+            conv.append({"m": mm, "side": sd, "h": hh, "steps": rc["steps"], "converged": bool(rc["converged"]),
+                         "err_inf": rc["err_inf"], "err_mean_abs": rc["err_mean_abs"]})
+            _progress(f"mixed_bc m={mm} side={sd}: {rc['steps']} steps, err_inf {rc['err_inf']:.3e}")
+            q.close()
+    slopes = {}
+    for mm in conv_orders:
+        r = [x for x in conv if x["m"] == mm]
+        slopes[str(mm)] = round(float(np.polyfit(np.log([x["h"] for x in r]), np.log([x["err_inf"] for x in r]),
+                                                 1)[0]), 3)
+    return {"workload": f"mixed_bc: [0,1/2]^3, {side}^3 jittered grid (seed {seed}), Dirichlet on the outer faces, "
+                        f"zero normal derivative on the inner faces, m={m}, n={n}, dt={alpha}*h^2/6",
+            "interior_nodes": nint, "neumann_nodes": nneu, "setup_s": round(setup, 3),
+            "ms_per_step_device": 1e3 * per_step, "ms_per_step_wall": 1e3 * wall / steps,
+            "node_updates_per_s": nint / per_step,
+            "alg_GBps_interior_sweep": round(nint * (12 * n + 24) / per_step / 1e9, 1),
+            "convergence": conv, "err_inf_slope_vs_h": slopes}
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
+
+
 def stream_ceiling(nbytes=1 << 30, reps=20):
     """Achievable HBM rates on this device for context: a 1 GiB device copy
     (read + write) and a 1 GiB read-only sum, timed with events."""
@@ -409,7 +555,8 @@ def main():
     ap.add_argument("--tte-target", type=float, default=1e-6)
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--workload", default="cube1M",
-                    choices=["cube1M", "cube8M", "cube4M_bands", "cube2M_adjoint", "support_sweep"],
+                    choices=["cube1M", "cube8M", "cube4M_bands", "cube2M_adjoint", "support_sweep", "order_scan",
+                             "mixed_bc"],
                     help="cube1M: the benchmark line; the others print their own measurement line")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32_refine"], help="cube8M: iteration mode")
     args = ap.parse_args()
@@ -430,6 +577,10 @@ def main():
             out = run_cube4m_bands()
         elif args.workload == "support_sweep":
             out = run_support_sweep()
+        elif args.workload == "order_scan":
+            out = run_order_scan()
+        elif args.workload == "mixed_bc":
+            out = run_mixed_bc()
         else:
             out = run_cube2m_adjoint()
         out["device"] = torch.cuda.get_device_name(0)

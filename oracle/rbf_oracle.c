@@ -360,13 +360,14 @@ static double nanmax_abs(double acc, double v)
     return (a > acc) ? a : acc;
 }
 
-/* (L u)_r = sum_k w_rk u_{idx_rk} in stencil order, for interior rows; 0 on
- * Dirichlet rows. */
+/* (L u)_r = sum_k w_rk u_{idx_rk} in stencil order: the Laplacian on
+ * interior rows, the normal derivative on Neumann rows (their weights, own
+ * entry included); 0 on Dirichlet rows. */
 void orc_apply(int64_t N, const int8_t *type, const int32_t *idx, const double *w,
                int n_stride, const int32_t *n_row, const double *u, double *Lu)
 {
     for (int64_t r = 0; r < N; ++r) {
-        if (type[r] != 0) { Lu[r] = 0.0; continue; }
+        if (type[r] == 1) { Lu[r] = 0.0; continue; }
         int n = n_row ? n_row[r] : n_stride;
         double acc = 0.0;
         for (int k = 0; k < n; ++k) {

@@ -29,6 +29,18 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblk, int rema
     return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
 }
 
+// Slice of the calling wavefront.  flags bit 0: XCD remap; bit 1: visit the
+// slices in reverse order (the odd sweeps of a zig-zag sequence, which start
+// where the previous sweep ended, on lines still held by the memory-side
+// Infinity Cache).  The row order within a sweep does not change results.
+template <int WAVES>
+__device__ __forceinline__ int64_t slice_index(int64_t nslices, int flags) {
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, flags & 1);
+    int64_t s = blk * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if ((flags & 2) && s < nslices) s = nslices - 1 - s;
+    return s;
+}
+
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -217,9 +229,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
     const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ f,
     const double *__restrict__ u_old, double *__restrict__ u_new, double dt, unsigned long long *res_slot,
-    int remap) {
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
-    const int64_t slice = blk * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int order) {
+    const int64_t slice = slice_index<WAVES>(nslices, order);
     const int lane = threadIdx.x & 63;
     unsigned long long bits = 0;
     if (slice < nslices) {
@@ -240,9 +251,8 @@ template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep_f32(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
     const float *__restrict__ w, int64_t nslices, int64_t N_int, const float *__restrict__ r,
-    const float *__restrict__ e_old, float *__restrict__ e_new, float dt, int remap) {
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
-    const int64_t slice = blk * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const float *__restrict__ e_old, float *__restrict__ e_new, float dt, int order) {
+    const int64_t slice = slice_index<WAVES>(nslices, order);
     const int lane = threadIdx.x & 63;
     if (slice >= nslices) return;
     const int len = slice_len[slice];
@@ -256,9 +266,8 @@ template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_apply_f64(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
     const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ u,
-    double *__restrict__ Lu, const double *__restrict__ f, unsigned long long *res_slot, int remap) {
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
-    const int64_t slice = blk * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *__restrict__ Lu, const double *__restrict__ f, unsigned long long *res_slot, int order) {
+    const int64_t slice = slice_index<WAVES>(nslices, order);
     const int lane = threadIdx.x & 63;
     unsigned long long bits = 0;
     if (slice < nslices) {
@@ -280,9 +289,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_outer_residual(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
     const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ f,
     const double *__restrict__ u, float *__restrict__ r32, float *__restrict__ e0, unsigned long long *res_slot,
-    int remap) {
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
-    const int64_t slice = blk * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int order) {
+    const int64_t slice = slice_index<WAVES>(nslices, order);
     const int lane = threadIdx.x & 63;
     unsigned long long bits = 0;
     if (slice < nslices) {
@@ -305,9 +313,8 @@ template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_adjoint_gather(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
     const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ lam_old,
-    double *__restrict__ lam_new, double *__restrict__ acc, double dt, int remap) {
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
-    const int64_t slice = blk * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *__restrict__ lam_new, double *__restrict__ acc, double dt, int order) {
+    const int64_t slice = slice_index<WAVES>(nslices, order);
     const int lane = threadIdx.x & 63;
     if (slice >= nslices) return;
     const int len = slice_len[slice];
@@ -607,14 +614,17 @@ hipError_t launch_neumann_apply(hipStream_t s, const Ell &e, int64_t N_int, int6
     return hipGetLastError();
 }
 
+inline int order_flags(const SweepCfg &c, int parity) { return c.xcd_remap | ((c.zigzag && (parity & 1)) ? 2 : 0); }
+
 hipError_t launch_sweep_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
-                            const double *u_old, double *u_new, double dt, unsigned long long *res_slot) {
-    return dispatch_shape<SweepF64>(c, e.layout, s, e, N_int, f, u_old, u_new, dt, res_slot, c.xcd_remap);
+                            const double *u_old, double *u_new, double dt, unsigned long long *res_slot,
+                            int parity) {
+    return dispatch_shape<SweepF64>(c, e.layout, s, e, N_int, f, u_old, u_new, dt, res_slot, order_flags(c, parity));
 }
 
 hipError_t launch_sweep_f32(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const float *r,
-                            const float *e_old, float *e_new, float dt) {
-    return dispatch_shape<SweepF32>(c, e.layout, s, e, N_int, r, e_old, e_new, dt, c.xcd_remap);
+                            const float *e_old, float *e_new, float dt, int parity) {
+    return dispatch_shape<SweepF32>(c, e.layout, s, e, N_int, r, e_old, e_new, dt, order_flags(c, parity));
 }
 
 hipError_t launch_apply_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *u,
@@ -628,8 +638,8 @@ hipError_t launch_outer_residual(hipStream_t s, const SweepCfg &c, const Ell &e,
 }
 
 hipError_t launch_adjoint_gather(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *lam_old,
-                                 double *lam_new, double *acc, double dt) {
-    return dispatch_shape<AdjGather>(c, e.layout, s, e, N_int, lam_old, lam_new, acc, dt, c.xcd_remap);
+                                 double *lam_new, double *acc, double dt, int parity) {
+    return dispatch_shape<AdjGather>(c, e.layout, s, e, N_int, lam_old, lam_new, acc, dt, order_flags(c, parity));
 }
 
 hipError_t launch_add_correction(hipStream_t s, int64_t N_int, double *u, const float *e) {

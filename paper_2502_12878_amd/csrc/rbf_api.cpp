@@ -592,6 +592,14 @@ static rbf_status make_ell(rbf_handle *h, int64_t row0, int64_t nrows, const std
     return RBF_OK;
 }
 
+// RBF_SWEEP_ZIGZAG=0/1 fixes the sweep order (forward only / alternating);
+// unset, the autotuner chooses.  Returns -1 when unset.
+static int zigzag_override() {
+    const char *z = std::getenv("RBF_SWEEP_ZIGZAG");
+    if (!z || !z[0]) return -1;
+    return z[0] == '1' ? 1 : 0;
+}
+
 // Internal order: interior rows by descending support size then canonical id,
 // then Neumann rows likewise, then Dirichlet rows by canonical id.
 static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
@@ -659,22 +667,27 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
     h->have_w32 = keep_fp32 != 0;
     // a tuned shape for this operator, if cached
     char key[160];
-    std::snprintf(key, sizeof key, "sweep|%s|L%d|%" PRId64 "|%" PRId64 "|%d", h->arch, e.layout, N_int, e.elems, e.max_len);
-    int v[4];
-    if (cache_lookup(key, v, 4)) {
+    std::snprintf(key, sizeof key, "sweepz|%s|L%d|%" PRId64 "|%" PRId64 "|%d", h->arch, e.layout, N_int, e.elems,
+                  e.max_len);
+    int v[5];
+    if (cache_lookup(key, v, 5)) {
         h->cfg.waves_per_block = v[0];
         h->cfg.unroll = v[1];
         h->cfg.xcd_remap = v[2];
         h->cfg.pipeline = e.layout ? v[3] : 0;
+        h->cfg.zigzag = v[4];
     }
-    std::snprintf(key, sizeof key, "sweep32|%s|L%d|%" PRId64 "|%" PRId64 "|%d", h->arch, e.layout, N_int, e.elems,
+    std::snprintf(key, sizeof key, "sweepz32|%s|L%d|%" PRId64 "|%" PRId64 "|%d", h->arch, e.layout, N_int, e.elems,
                   e.max_len);
-    if (cache_lookup(key, v, 4)) {
+    if (cache_lookup(key, v, 5)) {
         h->cfg32.waves_per_block = v[0];
         h->cfg32.unroll = v[1];
         h->cfg32.xcd_remap = v[2];
         h->cfg32.pipeline = e.layout ? v[3] : 0;
+        h->cfg32.zigzag = v[4];
     }
+    const int zz = zigzag_override();
+    if (zz >= 0) h->cfg.zigzag = h->cfg32.zigzag = zz;
     return RBF_OK;
 }
 
@@ -1040,7 +1053,7 @@ static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, d
             // Neumann rows first take their values from the current iterate
             if (h->N_neu > 0) e = launch_neumann_update(s, h->ellN, Ni, h->N_neu, h->wself, h->fint, a, b, h->nb);
             if (e == hipSuccess)
-                e = launch_sweep_f64(s, h->cfg, h->ell, Ni, h->fint, a, b, dt, report ? h->dslots : nullptr);
+                e = launch_sweep_f64(s, h->cfg, h->ell, Ni, h->fint, a, b, dt, report ? h->dslots : nullptr, (int)(i & 1));
             std::swap(a, b);
         }
     } else if (kind == kGraphMixed) {
@@ -1051,7 +1064,7 @@ static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, d
         float *a = h->ea, *b = h->eb;
         const float dt32 = (float)dt;
         for (int i = 0; i < inner && e == hipSuccess; ++i) {
-            e = launch_sweep_f32(s, h->cfg32, h->ell, Ni, h->r32, a, b, dt32);
+            e = launch_sweep_f32(s, h->cfg32, h->ell, Ni, h->r32, a, b, dt32, i & 1);
             std::swap(a, b);
         }
         if (e == hipSuccess) e = launch_add_correction(s, Ni, h->ua, a);
@@ -1069,7 +1082,7 @@ static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, d
         // ua and ub (from `start`), acc = tmp accumulates every new lam.
         double *a = start ? h->ub : h->ua, *b = start ? h->ua : h->ub;
         for (int64_t i = 0; i < steps && e == hipSuccess; ++i) {
-            e = launch_adjoint_gather(s, h->cfg, h->ellT, Ni, a, b, h->tmp, dt);
+            e = launch_adjoint_gather(s, h->cfg, h->ellT, Ni, a, b, h->tmp, dt, (int)(i & 1));
             std::swap(a, b);
         }
     }
@@ -1380,20 +1393,23 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
         auto launch = [&](const SweepCfg &c, int r) -> hipError_t {
             if (prec)
                 return launch_sweep_f32(h->stream, c, h->ell, Ni, h->r32, (r & 1) ? h->eb : h->ea,
-                                        (r & 1) ? h->ea : h->eb, 0.0f);
+                                        (r & 1) ? h->ea : h->eb, 0.0f, r & 1);
             return launch_sweep_f64(h->stream, c, h->ell, Ni, h->fint, (r & 1) ? h->ub : h->ua,
-                                    (r & 1) ? h->ua : h->ub, 0.0, nullptr);
+                                    (r & 1) ? h->ua : h->ub, 0.0, nullptr, r & 1);
         };
         for (int wv : {2, 4, 8})
             for (int un : {4, 8, 16})
                 for (int rm : {0, 1})
-                    for (int pl : {0, 1}) {
+                    for (int pl : {0, 1})
+                    for (int zz : {0, 1}) {
                         if (pl && h->ell.layout == 0) continue;
+                        if (zigzag_override() >= 0 && zz != zigzag_override()) continue;
                         SweepCfg c;
                         c.waves_per_block = wv;
                         c.unroll = un;
                         c.xcd_remap = rm;
                         c.pipeline = pl;
+                        c.zigzag = zz;
                         HIPCHK(h, launch(c, 0));
                         HIPCHK(h, hipEventRecord(h->ev0, h->stream));
                         for (int r = 0; r < reps; ++r) HIPCHK(h, launch(c, r));
@@ -1408,10 +1424,10 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
                     }
         (prec ? h->cfg32 : h->cfg) = bestc;
         char key[160];
-        std::snprintf(key, sizeof key, "%s|%s|L%d|%" PRId64 "|%" PRId64 "|%d", prec ? "sweep32" : "sweep", h->arch,
+        std::snprintf(key, sizeof key, "%s|%s|L%d|%" PRId64 "|%" PRId64 "|%d", prec ? "sweepz32" : "sweepz", h->arch,
                       h->ell.layout, Ni, h->ell.elems, h->ell.max_len);
-        int v[4] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap, bestc.pipeline};
-        cache_store(key, v, 4);
+        int v[5] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap, bestc.pipeline, bestc.zigzag};
+        cache_store(key, v, 5);
     }
     // leave the FP32 work vectors as the mixed loop expects them (0 beyond N_int)
     HIPCHK(h, launch_fill_f32(h->stream, h->N, 0.0f, h->ea));

@@ -33,9 +33,10 @@ struct SweepCfg {
     int unroll = 8;           // support entries loaded ahead per lane
     int xcd_remap = 1;        // give each XCD a contiguous range of slices
     int pipeline = 0;         // request the next group's streams before the current gathers
+    int zigzag = 0;           // odd sweeps of a sequence visit the slices in reverse order
     bool operator<(const SweepCfg &o) const {
-        return std::tie(waves_per_block, unroll, xcd_remap, pipeline) <
-               std::tie(o.waves_per_block, o.unroll, o.xcd_remap, o.pipeline);
+        return std::tie(waves_per_block, unroll, xcd_remap, pipeline, zigzag) <
+               std::tie(o.waves_per_block, o.unroll, o.xcd_remap, o.pipeline, o.zigzag);
     }
 };
 
@@ -170,17 +171,19 @@ hipError_t launch_neumann_update(hipStream_t s, const Ell &e, int64_t N_int, int
                                  const double *g, double *u_cur, double *u_next, double *nb);
 hipError_t launch_neumann_apply(hipStream_t s, const Ell &e, int64_t N_int, int64_t N_neu, const double *wself,
                                 const double *u, double *out);
+// parity: index of the sweep within its sequence (odd sweeps run reversed when c.zigzag is set)
 hipError_t launch_sweep_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
-                            const double *u_old, double *u_new, double dt, unsigned long long *res_slot);
+                            const double *u_old, double *u_new, double dt, unsigned long long *res_slot,
+                            int parity);
 hipError_t launch_sweep_f32(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const float *r,
-                            const float *e_old, float *e_new, float dt);
+                            const float *e_old, float *e_new, float dt, int parity);
 hipError_t launch_apply_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *u,
                             double *Lu, const double *f, unsigned long long *res_slot);
 hipError_t launch_outer_residual(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
                                  const double *u, float *r32, float *e0, unsigned long long *res_slot);
 hipError_t launch_add_correction(hipStream_t s, int64_t N_int, double *u, const float *e);
 hipError_t launch_adjoint_gather(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *lam_old,
-                                 double *lam_new, double *acc, double dt);
+                                 double *lam_new, double *acc, double dt, int parity);
 hipError_t launch_tcount(hipStream_t s, int64_t N, int32_t n_max, int64_t N_int, const int8_t *type,
                          const int32_t *iperm, const int32_t *sten, const int16_t *nrow, int32_t *cnt);
 hipError_t launch_tfill(hipStream_t s, int64_t N, int32_t n_max, int64_t N_int, const int8_t *type,

@@ -152,3 +152,16 @@ def test_mixed_error_slope(dim, sides, m):
         hs.append(0.5 / (side - 1))
     slope = np.polyfit(np.log(hs), np.log(errs), 1)[0]
     assert slope >= m - 1.3, (errs, slope)
+
+
+def test_apply_gives_normal_derivative_of_linear_fields():
+    """On Neumann rows the operator returns n . grad u, exact for linear u
+    (up to rounding); interior rows give 0 for a linear u, Dirichlet rows 0."""
+    dim, side, m = 3, 9, 4
+    xyz, typ, normals, idx, w = _mixed_problem(dim, side, m)
+    a = np.array([0.3, -1.1, 0.7])
+    Lu = oracle.Operator(typ, idx, w).apply(0.5 + a @ xyz)
+    B = typ == 2
+    assert np.abs(Lu[B] - a @ normals[:, B]).max() <= 1e-10
+    assert np.abs(Lu[typ == 0]).max() <= 1e-8
+    assert (Lu[typ == 1] == 0).all()
