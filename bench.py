@@ -596,10 +596,15 @@ def main():
         wall, per_sweep, nsw, rep = time_sweeps(s, args.steps, args.warmup)
         bytes_per_update = 12 * wl.n + 24
         alg_bytes = bytes_per_update * nint
+        info = s["p"].operator_info()
         entry = {"m": m, "n": wl.n, "interior_nodes": nint, "node_updates_per_s": nint * args.steps / wall,
                  "ms_per_step": 1e3 * wall / args.steps, "kernel_ms_per_sweep": 1e3 * per_sweep,
                  "alg_bytes_per_update": bytes_per_update, "alg_GBps": alg_bytes / per_sweep / 1e9,
                  "hbm_frac": alg_bytes / per_sweep / 1e9 / PEAK_HBM_GBS, "res_final": rep["res_final"],
+                 "format_bytes_per_sweep": info["stream_bytes_f64"],
+                 "format_GBps": info["stream_bytes_f64"] / per_sweep / 1e9,
+                 "sweep_shape": {k[4:]: v for k, v in info.items() if k.startswith("f64_")},
+                 "coded_slices_frac": round(info["coded_slices"] / max(1, info["slices"]), 4),
                  "setup": {k: round(v, 3) for k, v in s["setup"].items()}}
         per_order[m] = entry
         if i == 0:
@@ -614,7 +619,9 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(alg_bytes / per_sweep / 1e9, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(alg_bytes / per_sweep / 1e9 / PEAK_HBM_GBS, 4),
                 "traffic": traffic, "kernel": "k_sweep_f64", "alg_bytes_per_launch": alg_bytes,
-                "avg_launch_ms": round(1e3 * per_sweep, 5), "launches_timed": nsw}
+                "avg_launch_ms": round(1e3 * per_sweep, 5), "launches_timed": nsw,
+                "format_bytes_per_launch": entry["format_bytes_per_sweep"],
+                "format_frac": round(entry["format_GBps"] / PEAK_HBM_GBS, 4), "sweep_shape": entry["sweep_shape"]}
     tte = None if args.no_tte else time_to_error(s, args.tte_target)
     cpu = None if args.no_cpu else cpu_baseline()
     out = {"metric": "sweep node-updates/s + HBM GB/s; time to L-inf err 1e-6, FP32+refine vs FP64",

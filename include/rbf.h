@@ -260,11 +260,32 @@ rbf_status rbf_set_weights(rbf_handle *h, const double *w_host, int keep_fp32);
 /* ------------------------------------------------------------ tuning */
 
 /* Time candidate kernel shapes for the current operator and keep the fastest
- * (sweep: rows per workgroup, unroll depth, XCD-aware block order; weight
- * solver: panel width).  Results are cached in the JSON file named by the
+ * (sweep: rows per workgroup, unroll depth, XCD-aware block order, software
+ * pipelining, zig-zag slice order, 16-bit column codes; weight solver: panel
+ * width).  Results are cached in the JSON file named by the
  * RBF_AUTOTUNE_CACHE environment variable (none: not cached), keyed by device
- * architecture and problem shape.  Synchronises. */
+ * architecture and problem shape.  RBF_SWEEP_ZIGZAG=0/1 and
+ * RBF_SWEEP_CODES=0/1 fix those two choices.  Synchronises. */
 rbf_status rbf_autotune(rbf_handle *h);
+
+/* Layout of the packed interior operator and the sweep shapes in use.
+ * stream_bytes_* are the bytes one sweep reads and writes as the operator is
+ * stored: column ids (4 B) or codes (2 B, plus the per-slice segment table)
+ * and weights (8 B FP64 / 4 B FP32) of every slot including padding, slice
+ * headers, and f, u and u_new of each interior row (8 B each in FP64; r, e
+ * and e_new 4 B each in FP32).  The gathered values of u are not counted. */
+typedef struct {
+    int64_t n_interior, n_neumann;
+    int64_t slices, slots;          /* slots: packed entries incl. padding */
+    int64_t coded_slices;           /* slices whose ids are also stored as codes */
+    int32_t max_len, layout;
+    int32_t f64_waves, f64_unroll, f64_xcd_remap, f64_pipeline, f64_zigzag, f64_codes;
+    int32_t f32_waves, f32_unroll, f32_xcd_remap, f32_pipeline, f32_zigzag, f32_codes;
+    double stream_bytes_f64, stream_bytes_f32;
+} rbf_operator_info;
+
+/* Fill *info for the current operator (EINVAL without one). */
+rbf_status rbf_get_operator_info(const rbf_handle *h, rbf_operator_info *info);
 
 /* Mean device time per FP64 sweep over the last rbf_iterate FP64 chunks
  * (GPU events around each graph launch divided by its step count), and the

@@ -156,6 +156,11 @@ class Problem:
     def autotune(self):
         self._check(self._lib.rbf_autotune(self.h), "autotune")
 
+    def operator_info(self) -> dict:
+        info = _abi.rbf_operator_info()
+        self._check(self._lib.rbf_get_operator_info(self.h, C.byref(info)), "operator_info")
+        return info.as_dict()
+
     def last_sweep_time(self):
         s, n = C.c_double(), C.c_int64()
         self._check(self._lib.rbf_last_sweep_time(self.h, C.byref(s), C.byref(n)), "last_sweep_time")

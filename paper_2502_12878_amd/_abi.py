@@ -44,6 +44,19 @@ class rbf_iter_report(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class rbf_operator_info(C.Structure):
+    _fields_ = [("n_interior", C.c_int64), ("n_neumann", C.c_int64), ("slices", C.c_int64), ("slots", C.c_int64),
+                ("coded_slices", C.c_int64), ("max_len", C.c_int32), ("layout", C.c_int32),
+                ("f64_waves", C.c_int32), ("f64_unroll", C.c_int32), ("f64_xcd_remap", C.c_int32),
+                ("f64_pipeline", C.c_int32), ("f64_zigzag", C.c_int32), ("f64_codes", C.c_int32),
+                ("f32_waves", C.c_int32), ("f32_unroll", C.c_int32), ("f32_xcd_remap", C.c_int32),
+                ("f32_pipeline", C.c_int32), ("f32_zigzag", C.c_int32), ("f32_codes", C.c_int32),
+                ("stream_bytes_f64", C.c_double), ("stream_bytes_f32", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _h = C.c_void_p
 _p = C.c_void_p
 _st = C.c_int32
@@ -74,6 +87,7 @@ SIGNATURES = {
     "rbf_set_weights": (_st, [_h, _p, C.c_int]),
     "rbf_autotune": (_st, [_h]),
     "rbf_last_sweep_time": (_st, [_h, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "rbf_get_operator_info": (_st, [_h, C.POINTER(rbf_operator_info)]),
 }
 
 _lib = None

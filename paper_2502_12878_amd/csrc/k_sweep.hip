@@ -223,11 +223,91 @@ struct RowDot<T, U, 2> {
     }
 };
 
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+
+// Column of a 16-bit code: the segment base is held by lane `segment` of the
+// wavefront (segreg = segbase[16 s + lane % 16]) and fetched by a lane permute.
+__device__ __forceinline__ int32_t code_col(uint32_t c, int32_t segreg) {
+    return __builtin_amdgcn_ds_bpermute((int)((c >> 10) & 0x3cu), segreg) + (int32_t)(c & 0xfffu);
+}
+
+// Compressed rows (Ell::code): 4 codes per 8-byte vector, weights as pairs
+// (layout 1); len is even, codes are padded to a multiple of 4.
+template <typename T, int U>
+struct RowDotC {
+    static_assert(U % 4 == 0, "groups of whole code vectors");
+    __device__ static __forceinline__ T run(const uint16_t *__restrict__ code, int32_t segreg,
+                                            const T *__restrict__ w, const T *__restrict__ x, int lane, int len) {
+        typedef typename Vec2<T>::type V;
+        T acc = T(0);
+        const u16x4 *cp = (const u16x4 *)code + lane;
+        const V *wp = (const V *)w + lane;
+        int k = 0;
+        for (; k + U <= len; k += U) {
+            u16x4 c[U / 4];
+            V ww[U / 2];
+#pragma unroll
+            for (int q = 0; q < U / 4; ++q) c[q] = __builtin_nontemporal_load(cp + ((k >> 2) + q) * kSlice);
+#pragma unroll
+            for (int q = 0; q < U / 2; ++q) ww[q] = __builtin_nontemporal_load(wp + ((k >> 1) + q) * kSlice);
+            T xx[U];
+#pragma unroll
+            for (int q = 0; q < U / 4; ++q) {
+                xx[4 * q] = x[code_col(c[q].x, segreg)];
+                xx[4 * q + 1] = x[code_col(c[q].y, segreg)];
+                xx[4 * q + 2] = x[code_col(c[q].z, segreg)];
+                xx[4 * q + 3] = x[code_col(c[q].w, segreg)];
+            }
+#pragma unroll
+            for (int q = 0; q < U / 2; ++q) {
+                acc = fma(ww[q].x, xx[2 * q], acc);
+                acc = fma(ww[q].y, xx[2 * q + 1], acc);
+            }
+        }
+        for (; k < len; k += 2) {
+            const u16x4 c = __builtin_nontemporal_load(cp + (k >> 2) * kSlice);
+            const V ww = __builtin_nontemporal_load(wp + (k >> 1) * kSlice);
+            const uint32_t c0 = (k & 2) ? c.z : c.x, c1 = (k & 2) ? c.w : c.y;
+            acc = fma(ww.x, x[code_col(c0, segreg)], acc);
+            acc = fma(ww.y, x[code_col(c1, segreg)], acc);
+        }
+        return acc;
+    }
+};
+
+// Compressed view of a packed operator handed to the sweep kernels (all null
+// when the plain column ids are read).
+struct Codes {
+    const uint16_t *code;
+    const int64_t *cptr;
+    const int32_t *segbase;
+    const int8_t *cmode;
+};
+
+// Row sum of the calling lane's row of `slice`, from codes where the slice
+// has them, else from the 32-bit ids.
+// LAYOUT 3 is layout 1 read through the codes (kernels compiled for it hold
+// both loops; the others hold only their own, which keeps their registers).
+template <typename T, int U, int LAYOUT>
+__device__ __forceinline__ T row_dot(const Codes &cs, const int64_t *__restrict__ slice_ptr,
+                                     const int32_t *__restrict__ idx, const T *__restrict__ w,
+                                     const T *__restrict__ x, int64_t slice, int lane, int len) {
+    if constexpr (LAYOUT == 3) {
+        if (cs.cmode[slice]) {
+            const int32_t segreg = cs.segbase[slice * kSegs + (lane & (kSegs - 1))];
+            return RowDotC<T, U>::run(cs.code + cs.cptr[slice], segreg, w + slice_ptr[slice], x, lane, len);
+        }
+        return RowDot<T, U, 1>::run(idx, w, x, slice_ptr[slice], lane, len);
+    } else {
+        return RowDot<T, U, LAYOUT>::run(idx, w, x, slice_ptr[slice], lane, len);
+    }
+}
+
 // One explicit step on every interior row; optionally max |rho| into slot.
 template <int WAVES, int U, int LAYOUT, bool REDUCE>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
-    const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ f,
+    const double *__restrict__ w, Codes cs, int64_t nslices, int64_t N_int, const double *__restrict__ f,
     const double *__restrict__ u_old, double *__restrict__ u_new, double dt, unsigned long long *res_slot,
     int order) {
     const int64_t slice = slice_index<WAVES>(nslices, order);
@@ -235,7 +315,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
     unsigned long long bits = 0;
     if (slice < nslices) {
         const int len = slice_len[slice];
-        const double acc = RowDot<double, U, LAYOUT>::run(idx, w, u_old, slice_ptr[slice], lane, len);
+        const double acc = row_dot<double, U, LAYOUT>(cs, slice_ptr, idx, w, u_old, slice, lane, len);
         const int64_t row = slice * kSlice + lane;
         if (row < N_int) {
             const double rho = acc - f[row];
@@ -250,13 +330,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
 template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep_f32(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
-    const float *__restrict__ w, int64_t nslices, int64_t N_int, const float *__restrict__ r,
+    const float *__restrict__ w, Codes cs, int64_t nslices, int64_t N_int, const float *__restrict__ r,
     const float *__restrict__ e_old, float *__restrict__ e_new, float dt, int order) {
     const int64_t slice = slice_index<WAVES>(nslices, order);
     const int lane = threadIdx.x & 63;
     if (slice >= nslices) return;
     const int len = slice_len[slice];
-    const float acc = RowDot<float, U, LAYOUT>::run(idx, w, e_old, slice_ptr[slice], lane, len);
+    const float acc = row_dot<float, U, LAYOUT>(cs, slice_ptr, idx, w, e_old, slice, lane, len);
     const int64_t row = slice * kSlice + lane;
     if (row < N_int) e_new[row] = e_old[row] + dt * (acc - r[row]);
 }
@@ -408,7 +488,7 @@ __global__ void k_pack_ell(int64_t row0, int64_t nrows, int32_t n_max, int32_t k
                            const int32_t *__restrict__ sten, const int16_t *__restrict__ nrow,
                            const double *__restrict__ w_can, const int64_t *__restrict__ slice_ptr,
                            const int32_t *__restrict__ slice_len, int32_t *__restrict__ idx, double *__restrict__ w,
-                           float *__restrict__ w32, double *__restrict__ wself) {
+                           float *__restrict__ w32, double *__restrict__ wself, int32_t *__restrict__ foreign) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = t / kmax;
     const int k = (int)(t - i * kmax);
@@ -438,6 +518,9 @@ __global__ void k_pack_ell(int64_t row0, int64_t nrows, int32_t n_max, int32_t k
                 wself[i] = wk;
                 wk = 0.0;
             }
+            // a support entry that is neither interior (internal id < row0)
+            // nor the row itself
+            if (foreign && col >= row0 && col != gi) *foreign = 1;
         }
     }
     const int64_t pos = ell_pos(layout, base, slot, lane);
@@ -448,11 +531,14 @@ __global__ void k_pack_ell(int64_t row0, int64_t nrows, int32_t n_max, int32_t k
 
 // Neumann update, first half: nb[j] = (g_j - sum_{k != self} w_jk u_k) / w_jj
 // for Neumann row j (internal row N_int + j), all from the current iterate.
+// With u_store (supports of interior nodes and the row itself only, so no
+// Neumann row reads another's value) the new value goes straight into both
+// iterate buffers: u_store[0] = the current one, u_store[1] = the next.
 template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_neumann_eval(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
     const double *__restrict__ w, int64_t nslices, int64_t N_int, int64_t N_neu, const double *__restrict__ wself,
-    const double *__restrict__ g, const double *__restrict__ u, double *__restrict__ nb) {
+    const double *__restrict__ g, const double *u, double *__restrict__ nb, double *u_cur, double *u_next) {
     const int64_t slice = (int64_t)blockIdx.x * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (slice >= nslices) return;
@@ -460,8 +546,17 @@ __global__ __launch_bounds__(WAVES * 64) void k_neumann_eval(
     const double acc = RowDot<double, U, LAYOUT>::run(idx, w, u, slice_ptr[slice], lane, len);
     const int64_t j = slice * kSlice + lane;
     if (j >= N_neu) return;
-    if (g) nb[j] = (g[N_int + j] - acc) / wself[j];
-    else nb[N_int + j] = acc + wself[j] * u[N_int + j];  // without data: the derivative itself
+    if (g) {
+        const double v = (g[N_int + j] - acc) / wself[j];
+        if (u_cur) {
+            u_cur[N_int + j] = v;
+            u_next[N_int + j] = v;
+        } else {
+            nb[j] = v;
+        }
+    } else {
+        nb[N_int + j] = acc + wself[j] * u[N_int + j];  // without data: the derivative itself
+    }
 }
 
 // Neumann update, second half: store the new values in both iterate buffers.
@@ -511,18 +606,36 @@ hipError_t dispatch_shape(const SweepCfg &c, int layout, A &&...a) {
     return hipErrorInvalidValue;
 }
 
+// The same over the shapes of the sweeps that read codes (LAYOUT 3).
+template <template <int, int, int> class F, typename... A>
+hipError_t dispatch_codes(const SweepCfg &c, A &&...a) {
+#define RBF_CASE(WV, UN) \
+    if (c.waves_per_block == WV && c.unroll == UN) return F<WV, UN, 3>::run(a...);
+    RBF_CASE(2, 4) RBF_CASE(2, 8) RBF_CASE(2, 16)
+    RBF_CASE(4, 4) RBF_CASE(4, 8) RBF_CASE(4, 16)
+    RBF_CASE(8, 4) RBF_CASE(8, 8) RBF_CASE(8, 16)
+#undef RBF_CASE
+    return hipErrorInvalidValue;
+}
+
+// Whether a sweep with shape c reads the codes of e.
+inline bool use_codes(const SweepCfg &c, const Ell &e) { return c.codes && e.layout == 1 && e.cmode; }
+
+inline Codes codes_of(const Ell &e) { return Codes{e.code, e.cptr, e.segbase, e.cmode}; }
+
 template <int WV, int UN, int LY>
 struct SweepF64 {
     static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const double *f, const double *uo, double *un,
                           double dt, unsigned long long *slot, int remap) {
         if (!e.nslices) return hipSuccess;
         const unsigned g = grid1d(e.nslices, WV);
+        const Codes cs = codes_of(e);
         if (slot)
             hipLaunchKernelGGL((k_sweep_f64<WV, UN, LY, true>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr,
-                               e.slice_len, e.idx, e.w, e.nslices, N_int, f, uo, un, dt, slot, remap);
+                               e.slice_len, e.idx, e.w, cs, e.nslices, N_int, f, uo, un, dt, slot, remap);
         else
             hipLaunchKernelGGL((k_sweep_f64<WV, UN, LY, false>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr,
-                               e.slice_len, e.idx, e.w, e.nslices, N_int, f, uo, un, dt, slot, remap);
+                               e.slice_len, e.idx, e.w, cs, e.nslices, N_int, f, uo, un, dt, slot, remap);
         return hipGetLastError();
     }
 };
@@ -533,7 +646,8 @@ struct SweepF32 {
                           float dt, int remap) {
         if (!e.nslices) return hipSuccess;
         hipLaunchKernelGGL((k_sweep_f32<WV, UN, LY>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
-                           e.slice_ptr, e.slice_len, e.idx, e.w32, e.nslices, N_int, r, eo, en, dt, remap);
+                           e.slice_ptr, e.slice_len, e.idx, e.w32, codes_of(e), e.nslices, N_int, r, eo, en, dt,
+                           remap);
         return hipGetLastError();
     }
 };
@@ -575,28 +689,101 @@ struct OuterRes {
 
 hipError_t launch_pack_ell(hipStream_t s, int64_t row0, int64_t nrows, int32_t n_max, const int32_t *perm,
                            const int32_t *iperm, const int32_t *sten, const int16_t *nrow, const double *w_can,
-                           const Ell &e, double *wself) {
+                           const Ell &e, double *wself, int32_t *foreign) {
     const int32_t kmax = e.max_len;
     const int64_t total = e.nslices * kSlice * (int64_t)kmax;
     if (!total) return hipSuccess;
     hipLaunchKernelGGL(k_pack_ell, dim3(grid1d(total, 256)), dim3(256), 0, s, row0, nrows, n_max, kmax, e.nslices,
-                       e.layout, perm, iperm, sten, nrow, w_can, e.slice_ptr, e.slice_len, e.idx, e.w, e.w32, wself);
+                       e.layout, perm, iperm, sten, nrow, w_can, e.slice_ptr, e.slice_len, e.idx, e.w, e.w32, wself,
+                       foreign);
+    return hipGetLastError();
+}
+
+// Segment codes of one slice per workgroup (one wavefront): the distinct
+// aligned 4096-id blocks touched by any entry of the slice (padding entries
+// included, so every stored column stays encodable) are found in ascending
+// order by repeated wavefront minima; with at most kSegs of them the slice
+// gets codes (cmode 1), else it keeps only its 32-bit ids (cmode 0).
+__global__ __launch_bounds__(64) void k_encode_codes(const int64_t *__restrict__ slice_ptr,
+                                                     const int32_t *__restrict__ slice_len,
+                                                     const int32_t *__restrict__ idx, int64_t nslices,
+                                                     const int64_t *__restrict__ cptr, uint16_t *__restrict__ code,
+                                                     int32_t *__restrict__ segbase, int8_t *__restrict__ cmode) {
+    __shared__ uint16_t blk[kMaxSupport * kSlice];
+    __shared__ int32_t list[kSegs];
+    const int64_t s = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int len = slice_len[s];
+    const int64_t base = slice_ptr[s];
+    for (int k = 0; k < len; ++k) blk[k * kSlice + lane] = (uint16_t)(idx[ell_pos(1, base, k, lane)] >> 12);
+    __syncthreads();
+    int cnt = 0, cur = -1;
+    bool over = false;
+    for (int it = 0; it <= kSegs; ++it) {
+        int mn = 0x7fffffff;
+        for (int k = 0; k < len; ++k) {
+            const int v = blk[k * kSlice + lane];
+            if (v > cur && v < mn) mn = v;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const int o = __shfl_xor(mn, off, 64);
+            mn = o < mn ? o : mn;
+        }
+        if (mn == 0x7fffffff) break;
+        if (cnt == kSegs) {
+            over = true;
+            break;
+        }
+        if (lane == 0) list[cnt] = mn;
+        ++cnt;
+        cur = mn;
+    }
+    __syncthreads();
+    if (over) {
+        if (lane == 0) cmode[s] = 0;
+        return;
+    }
+    if (lane < kSegs) segbase[s * kSegs + lane] = (lane < cnt ? list[lane] : list[0]) << 12;
+    if (lane == 0) cmode[s] = 1;
+    const int len4 = (len + 3) & ~3;
+    uint16_t *out = code + cptr[s];
+    for (int k = 0; k < len4; ++k) {
+        uint16_t c = 0;
+        if (k < len) {
+            const int32_t col = idx[ell_pos(1, base, k, lane)];
+            const int b = col >> 12;
+            int seg = 0;
+            while (seg + 1 < cnt && list[seg] != b) ++seg;
+            c = (uint16_t)((seg << 12) | (col & (kSegSpan - 1)));
+        }
+        out[(int64_t)(k >> 2) * (4 * kSlice) + 4 * lane + (k & 3)] = c;
+    }
+}
+
+hipError_t launch_encode_codes(hipStream_t s, const Ell &e) {
+    if (!e.nslices || e.layout != 1 || !e.code) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_encode_codes, dim3((unsigned)e.nslices), dim3(kSlice), 0, s, e.slice_ptr, e.slice_len, e.idx,
+                       e.nslices, e.cptr, e.code, e.segbase, e.cmode);
     return hipGetLastError();
 }
 
 // The Neumann update of one step (evaluate all new boundary values from the
 // current iterate, then store them in both buffers).
 hipError_t launch_neumann_update(hipStream_t s, const Ell &e, int64_t N_int, int64_t N_neu, const double *wself,
-                                 const double *g, double *u_cur, double *u_next, double *nb) {
+                                 const double *g, double *u_cur, double *u_next, double *nb, bool direct) {
     if (!e.nslices) return hipSuccess;
     const unsigned grid = grid1d(e.nslices, 4);
+    double *uc = direct ? u_cur : nullptr, *un = direct ? u_next : nullptr;
     if (e.layout)
         hipLaunchKernelGGL((k_neumann_eval<4, 8, 1>), dim3(grid), dim3(256), 0, s, e.slice_ptr, e.slice_len, e.idx,
-                           e.w, e.nslices, N_int, N_neu, wself, g, u_cur, nb);
+                           e.w, e.nslices, N_int, N_neu, wself, g, u_cur, nb, uc, un);
     else
         hipLaunchKernelGGL((k_neumann_eval<4, 8, 0>), dim3(grid), dim3(256), 0, s, e.slice_ptr, e.slice_len, e.idx,
-                           e.w, e.nslices, N_int, N_neu, wself, g, u_cur, nb);
-    hipLaunchKernelGGL(k_neumann_store, dim3(grid1d(N_neu, 256)), dim3(256), 0, s, N_int, N_neu, nb, u_cur, u_next);
+                           e.w, e.nslices, N_int, N_neu, wself, g, u_cur, nb, uc, un);
+    if (!direct)
+        hipLaunchKernelGGL(k_neumann_store, dim3(grid1d(N_neu, 256)), dim3(256), 0, s, N_int, N_neu, nb, u_cur,
+                           u_next);
     return hipGetLastError();
 }
 
@@ -607,10 +794,10 @@ hipError_t launch_neumann_apply(hipStream_t s, const Ell &e, int64_t N_int, int6
     const unsigned grid = grid1d(e.nslices, 4);
     if (e.layout)
         hipLaunchKernelGGL((k_neumann_eval<4, 8, 1>), dim3(grid), dim3(256), 0, s, e.slice_ptr, e.slice_len, e.idx,
-                           e.w, e.nslices, N_int, N_neu, wself, nullptr, u, out);
+                           e.w, e.nslices, N_int, N_neu, wself, nullptr, u, out, nullptr, nullptr);
     else
         hipLaunchKernelGGL((k_neumann_eval<4, 8, 0>), dim3(grid), dim3(256), 0, s, e.slice_ptr, e.slice_len, e.idx,
-                           e.w, e.nslices, N_int, N_neu, wself, nullptr, u, out);
+                           e.w, e.nslices, N_int, N_neu, wself, nullptr, u, out, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -619,11 +806,15 @@ inline int order_flags(const SweepCfg &c, int parity) { return c.xcd_remap | ((c
 hipError_t launch_sweep_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
                             const double *u_old, double *u_new, double dt, unsigned long long *res_slot,
                             int parity) {
+    if (use_codes(c, e))
+        return dispatch_codes<SweepF64>(c, s, e, N_int, f, u_old, u_new, dt, res_slot, order_flags(c, parity));
     return dispatch_shape<SweepF64>(c, e.layout, s, e, N_int, f, u_old, u_new, dt, res_slot, order_flags(c, parity));
 }
 
 hipError_t launch_sweep_f32(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const float *r,
                             const float *e_old, float *e_new, float dt, int parity) {
+    if (use_codes(c, e))
+        return dispatch_codes<SweepF32>(c, s, e, N_int, r, e_old, e_new, dt, order_flags(c, parity));
     return dispatch_shape<SweepF32>(c, e.layout, s, e, N_int, r, e_old, e_new, dt, order_flags(c, parity));
 }
 

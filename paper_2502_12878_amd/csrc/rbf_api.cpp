@@ -109,6 +109,10 @@ void drop_operator(rbf_handle *h) {
     free_t(h, h->ell.idx);
     free_t(h, h->ell.w);
     free_t(h, h->ell.w32);
+    free_t(h, h->ell.code);
+    free_t(h, h->ell.cptr);
+    free_t(h, h->ell.segbase);
+    free_t(h, h->ell.cmode);
     h->ell = Ell{};
     free_t(h, h->ellT.slice_ptr);
     free_t(h, h->ellT.slice_len);
@@ -556,7 +560,7 @@ rbf_status rbf_build_stencils(rbf_handle *h, int32_t n_uniform, const int16_t *n
 // Sliced operator over internal rows [row0, row0 + nrows) (perm gives their
 // canonical ids); with wself, each row's own weight is split out (Neumann rows).
 static rbf_status make_ell(rbf_handle *h, int64_t row0, int64_t nrows, const std::vector<int32_t> &perm, int layout,
-                           int keep_fp32, Ell *out, double *wself) {
+                           int keep_fp32, Ell *out, double *wself, bool with_codes, int32_t *foreign = nullptr) {
     Ell e;
     e.layout = layout;
     e.nslices = (nrows + kSlice - 1) / kSlice;
@@ -587,18 +591,44 @@ static rbf_status make_ell(rbf_handle *h, int64_t row0, int64_t nrows, const std
     if (e.nslices) {
         HIPCHK(h, hipMemcpyAsync(e.slice_len, slen.data(), sizeof(int32_t) * e.nslices, hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, launch_pack_ell(h->stream, row0, nrows, h->n_max, h->perm, h->iperm, h->sten, h->nrow, h->w_can, e,
-                                  wself));
+                                  wself, foreign));
+    }
+    // 16-bit segment codes for the column ids (the sweeps' index stream at half
+    // the bytes); the block number of an id must fit in 16 bits
+    const char *cenv = std::getenv("RBF_ELL_CODES");
+    const bool want_codes = with_codes && e.layout == 1 && e.nslices && !(cenv && cenv[0] == '0') &&
+                            h->N < ((int64_t)1 << 28);
+    if (want_codes) {
+        std::vector<int64_t> cp((size_t)e.nslices + 1);
+        cp[0] = 0;
+        for (int64_t s = 0; s < e.nslices; ++s) cp[s + 1] = cp[s] + (int64_t)kSlice * ((slen[s] + 3) & ~3);
+        e.celems = cp[e.nslices];
+        ALLOC(h, e.code, uint16_t, e.celems);
+        ALLOC(h, e.cptr, int64_t, e.nslices + 1);
+        ALLOC(h, e.segbase, int32_t, (size_t)kSegs * e.nslices);
+        ALLOC(h, e.cmode, int8_t, e.nslices);
+        *out = e;
+        HIPCHK(h, hipMemcpyAsync(e.cptr, cp.data(), sizeof(int64_t) * (e.nslices + 1), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, launch_encode_codes(h->stream, e));
+        std::vector<int8_t> cm((size_t)e.nslices);
+        HIPCHK(h, hipMemcpyAsync(cm.data(), e.cmode, (size_t)e.nslices, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        for (int8_t c : cm) e.coded_slices += c;
+        *out = e;
     }
     return RBF_OK;
 }
 
-// RBF_SWEEP_ZIGZAG=0/1 fixes the sweep order (forward only / alternating);
-// unset, the autotuner chooses.  Returns -1 when unset.
-static int zigzag_override() {
-    const char *z = std::getenv("RBF_SWEEP_ZIGZAG");
+// RBF_SWEEP_ZIGZAG=0/1 fixes the sweep order (forward only / alternating) and
+// RBF_SWEEP_CODES=0/1 whether the sweeps read the 16-bit codes; unset, the
+// autotuner chooses.  -1 when unset.
+static int env_flag(const char *name) {
+    const char *z = std::getenv(name);
     if (!z || !z[0]) return -1;
     return z[0] == '1' ? 1 : 0;
 }
+static int zigzag_override() { return env_flag("RBF_SWEEP_ZIGZAG"); }
+static int codes_override() { return env_flag("RBF_SWEEP_CODES"); }
 
 // Internal order: interior rows by descending support size then canonical id,
 // then Neumann rows likewise, then Dirichlet rows by canonical id.
@@ -631,15 +661,20 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
     // packed layout: entry pairs as vectors unless RBF_ELL_LAYOUT=0
     const char *lay = std::getenv("RBF_ELL_LAYOUT");
     const int layout = (lay && lay[0] == '0') ? 0 : 1;
-    rbf_status st = make_ell(h, 0, N_int, perm, layout, keep_fp32, &h->ell, nullptr);
+    rbf_status st = make_ell(h, 0, N_int, perm, layout, keep_fp32, &h->ell, nullptr, true);
     if (st) return st;
     Ell &e = h->ell;
     if (N_neu > 0) {
         ALLOC(h, h->wself, double, N_neu);
         ALLOC(h, h->nb, double, N_neu);
         HIPCHK(h, launch_fill_f64(h->stream, N_neu, 0.0, h->wself));
-        st = make_ell(h, N_int, N_neu, perm, layout, 0, &h->ellN, h->wself);
+        HIPCHK(h, launch_fill_u64(h->stream, 1, 0ull, h->dslots + 3));
+        st = make_ell(h, N_int, N_neu, perm, layout, 0, &h->ellN, h->wself, false, (int32_t *)(h->dslots + 3));
         if (st) return st;
+        HIPCHK(h, hipMemcpyAsync(h->hslots + 3, h->dslots + 3, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                 h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        h->neu_direct = h->hslots[3] == 0;
         // each Neumann row divides by its own weight: it must be present and nonzero
         std::vector<double> ws((size_t)N_neu);
         HIPCHK(h, hipMemcpyAsync(ws.data(), h->wself, sizeof(double) * N_neu, hipMemcpyDeviceToHost, h->stream));
@@ -667,27 +702,23 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
     h->have_w32 = keep_fp32 != 0;
     // a tuned shape for this operator, if cached
     char key[160];
-    std::snprintf(key, sizeof key, "sweepz|%s|L%d|%" PRId64 "|%" PRId64 "|%d", h->arch, e.layout, N_int, e.elems,
-                  e.max_len);
-    int v[5];
-    if (cache_lookup(key, v, 5)) {
-        h->cfg.waves_per_block = v[0];
-        h->cfg.unroll = v[1];
-        h->cfg.xcd_remap = v[2];
-        h->cfg.pipeline = e.layout ? v[3] : 0;
-        h->cfg.zigzag = v[4];
-    }
-    std::snprintf(key, sizeof key, "sweepz32|%s|L%d|%" PRId64 "|%" PRId64 "|%d", h->arch, e.layout, N_int, e.elems,
-                  e.max_len);
-    if (cache_lookup(key, v, 5)) {
-        h->cfg32.waves_per_block = v[0];
-        h->cfg32.unroll = v[1];
-        h->cfg32.xcd_remap = v[2];
-        h->cfg32.pipeline = e.layout ? v[3] : 0;
-        h->cfg32.zigzag = v[4];
+    int v[6];
+    for (int prec = 0; prec < 2; ++prec) {
+        std::snprintf(key, sizeof key, "%s|%s|L%d|%" PRId64 "|%" PRId64 "|%d|c%" PRId64, prec ? "sweep32" : "sweep",
+                      h->arch, e.layout, N_int, e.elems, e.max_len, e.coded_slices);
+        if (!cache_lookup(key, v, 6)) continue;
+        SweepCfg &c = prec ? h->cfg32 : h->cfg;
+        c.waves_per_block = v[0];
+        c.unroll = v[1];
+        c.xcd_remap = v[2];
+        c.pipeline = e.layout ? v[3] : 0;
+        c.zigzag = v[4];
+        c.codes = e.cmode ? v[5] : 0;
     }
     const int zz = zigzag_override();
     if (zz >= 0) h->cfg.zigzag = h->cfg32.zigzag = zz;
+    const int cd = codes_override();
+    if (cd >= 0) h->cfg.codes = h->cfg32.codes = (cd && e.cmode) ? 1 : 0;
     return RBF_OK;
 }
 
@@ -1051,7 +1082,8 @@ static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, d
         for (int64_t i = 0; i < steps && e == hipSuccess; ++i) {
             const bool report = kind == kGraphF64 && i == steps - 1;
             // Neumann rows first take their values from the current iterate
-            if (h->N_neu > 0) e = launch_neumann_update(s, h->ellN, Ni, h->N_neu, h->wself, h->fint, a, b, h->nb);
+            if (h->N_neu > 0)
+                e = launch_neumann_update(s, h->ellN, Ni, h->N_neu, h->wself, h->fint, a, b, h->nb, h->neu_direct);
             if (e == hipSuccess)
                 e = launch_sweep_f64(s, h->cfg, h->ell, Ni, h->fint, a, b, dt, report ? h->dslots : nullptr, (int)(i & 1));
             std::swap(a, b);
@@ -1288,6 +1320,60 @@ extern "C" rbf_status rbf_iterate(rbf_handle *h, const double *f_dev, double *u_
     return RBF_OK;
 }
 
+// Bytes one sweep streams through the packed operator as stored (see the
+// header), for FP64 (wbytes 8, vbytes 8) or FP32 (4, 4) with or without codes.
+static double stream_bytes(const rbf_handle *h, int wbytes, int vbytes, bool codes) {
+    const Ell &e = h->ell;
+    if (!e.nslices) return 0.0;
+    std::vector<int32_t> slen((size_t)e.nslices);
+    std::vector<int8_t> cm;
+    if (hipMemcpy(slen.data(), e.slice_len, sizeof(int32_t) * e.nslices, hipMemcpyDeviceToHost) != hipSuccess)
+        return 0.0;
+    if (codes) {
+        cm.resize((size_t)e.nslices);
+        if (hipMemcpy(cm.data(), e.cmode, (size_t)e.nslices, hipMemcpyDeviceToHost) != hipSuccess) return 0.0;
+    }
+    double b = 0.0;
+    for (int64_t s = 0; s < e.nslices; ++s) {
+        const double len = slen[s], len4 = (slen[s] + 3) & ~3;
+        b += 12.0 + kSlice * len * wbytes;                                  // header, weights
+        if (codes && cm[s]) b += 1.0 + 4.0 * kSegs + 8.0 + kSlice * len4 * 2.0;  // mode, segments, offset, codes
+        else b += kSlice * len * 4.0;                                       // ids
+    }
+    return b + 3.0 * vbytes * (double)h->N_int;
+}
+
+extern "C" rbf_status rbf_get_operator_info(const rbf_handle *h, rbf_operator_info *info) {
+    if (!h || !info) return RBF_EINVAL;
+    if (!h->have_w || !h->ua) return RBF_EINVAL;
+    DeviceGuard g(h->device);
+    std::memset(info, 0, sizeof *info);
+    const Ell &e = h->ell;
+    info->n_interior = h->N_int;
+    info->n_neumann = h->N_neu;
+    info->slices = e.nslices;
+    info->slots = e.elems;
+    info->coded_slices = e.cmode ? e.coded_slices : 0;
+    info->max_len = e.max_len;
+    info->layout = e.layout;
+    const SweepCfg &a = h->cfg, &b = h->cfg32;
+    info->f64_waves = a.waves_per_block;
+    info->f64_unroll = a.unroll;
+    info->f64_xcd_remap = a.xcd_remap;
+    info->f64_pipeline = a.pipeline;
+    info->f64_zigzag = a.zigzag;
+    info->f64_codes = a.codes && e.cmode ? 1 : 0;
+    info->f32_waves = b.waves_per_block;
+    info->f32_unroll = b.unroll;
+    info->f32_xcd_remap = b.xcd_remap;
+    info->f32_pipeline = b.pipeline;
+    info->f32_zigzag = b.zigzag;
+    info->f32_codes = b.codes && e.cmode ? 1 : 0;
+    info->stream_bytes_f64 = stream_bytes(h, 8, 8, info->f64_codes);
+    info->stream_bytes_f32 = h->have_w32 ? stream_bytes(h, 4, 4, info->f32_codes) : 0.0;
+    return RBF_OK;
+}
+
 extern "C" rbf_status rbf_last_sweep_time(const rbf_handle *h, double *seconds_per_sweep, int64_t *sweeps) {
     if (!h) return RBF_EINVAL;
     if (seconds_per_sweep) *seconds_per_sweep = h->last_sweep_sec;
@@ -1401,15 +1487,20 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
             for (int un : {4, 8, 16})
                 for (int rm : {0, 1})
                     for (int pl : {0, 1})
-                    for (int zz : {0, 1}) {
+                    for (int zz : {0, 1})
+                    for (int cd : {0, 1}) {
                         if (pl && h->ell.layout == 0) continue;
                         if (zigzag_override() >= 0 && zz != zigzag_override()) continue;
+                        // codes are read by the plain paired loop only
+                        if (cd && (pl || !h->ell.cmode)) continue;
+                        if (codes_override() >= 0 && cd != codes_override() && h->ell.cmode) continue;
                         SweepCfg c;
                         c.waves_per_block = wv;
                         c.unroll = un;
                         c.xcd_remap = rm;
                         c.pipeline = pl;
                         c.zigzag = zz;
+                        c.codes = cd;
                         HIPCHK(h, launch(c, 0));
                         HIPCHK(h, hipEventRecord(h->ev0, h->stream));
                         for (int r = 0; r < reps; ++r) HIPCHK(h, launch(c, r));
@@ -1424,10 +1515,10 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
                     }
         (prec ? h->cfg32 : h->cfg) = bestc;
         char key[160];
-        std::snprintf(key, sizeof key, "%s|%s|L%d|%" PRId64 "|%" PRId64 "|%d", prec ? "sweepz32" : "sweepz", h->arch,
-                      h->ell.layout, Ni, h->ell.elems, h->ell.max_len);
-        int v[5] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap, bestc.pipeline, bestc.zigzag};
-        cache_store(key, v, 5);
+        std::snprintf(key, sizeof key, "%s|%s|L%d|%" PRId64 "|%" PRId64 "|%d|c%" PRId64, prec ? "sweep32" : "sweep",
+                      h->arch, h->ell.layout, Ni, h->ell.elems, h->ell.max_len, h->ell.coded_slices);
+        int v[6] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap, bestc.pipeline, bestc.zigzag, bestc.codes};
+        cache_store(key, v, 6);
     }
     // leave the FP32 work vectors as the mixed loop expects them (0 beyond N_int)
     HIPCHK(h, launch_fill_f32(h->stream, h->N, 0.0f, h->ea));

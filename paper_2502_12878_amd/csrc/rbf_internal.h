@@ -34,9 +34,10 @@ struct SweepCfg {
     int xcd_remap = 1;        // give each XCD a contiguous range of slices
     int pipeline = 0;         // request the next group's streams before the current gathers
     int zigzag = 0;           // odd sweeps of a sequence visit the slices in reverse order
+    int codes = 0;            // read 16-bit segment codes instead of 32-bit column ids (Ell::code)
     bool operator<(const SweepCfg &o) const {
-        return std::tie(waves_per_block, unroll, xcd_remap, pipeline, zigzag) <
-               std::tie(o.waves_per_block, o.unroll, o.xcd_remap, o.pipeline, o.zigzag);
+        return std::tie(waves_per_block, unroll, xcd_remap, pipeline, zigzag, codes) <
+               std::tie(o.waves_per_block, o.unroll, o.xcd_remap, o.pipeline, o.zigzag, o.codes);
     }
 };
 
@@ -55,7 +56,22 @@ struct Ell {
     int32_t *idx = nullptr;        // [elems] internal ids
     double *w = nullptr;           // [elems]
     float *w32 = nullptr;          // [elems] or null
+    // Compressed column ids (layout 1 only): the columns of a slice fall in at
+    // most kSegs aligned blocks of kSegSpan ids; entry k of a lane is the
+    // 16-bit code (segment << 12 | column % 4096) at cptr[s] + 256 (k / 4) +
+    // 4 lane + k % 4 (slice length padded to a multiple of 4), and
+    // column = segbase[16 s + segment] + (code & 4095).  Slices touching more
+    // blocks keep cmode[s] = 0 and are read from idx.
+    uint16_t *code = nullptr;      // [celems]
+    int64_t *cptr = nullptr;       // [nslices + 1]
+    int32_t *segbase = nullptr;    // [16 nslices]
+    int8_t *cmode = nullptr;       // [nslices] 1: slice has codes
+    int64_t celems = 0;
+    int64_t coded_slices = 0;      // slices with cmode 1
 };
+
+constexpr int kSegs = 16;
+constexpr int kSegSpan = 4096;
 
 }  // namespace rbf
 
@@ -98,6 +114,7 @@ struct rbf_handle {
     rbf::Ell ellN;             // Neumann rows (internal N_int ..), own entry zeroed
     double *wself = nullptr;   // [N_neu] own weight of each Neumann row
     double *nb = nullptr;      // [N_neu] new Neumann values of a step
+    bool neu_direct = false;   // Neumann supports hold interior nodes only: update in place
 
     // iteration vectors (internal order)
     double *ua = nullptr, *ub = nullptr, *fint = nullptr, *tmp = nullptr, *uref = nullptr;
@@ -166,9 +183,10 @@ hipError_t launch_weights_items(hipStream_t s, int dim, int64_t N, const double 
 // ---------------------------------------------------------------- sweep family
 hipError_t launch_pack_ell(hipStream_t s, int64_t row0, int64_t nrows, int32_t n_max, const int32_t *perm,
                            const int32_t *iperm, const int32_t *sten, const int16_t *nrow, const double *w_can,
-                           const Ell &e, double *wself);
+                           const Ell &e, double *wself, int32_t *foreign);
+hipError_t launch_encode_codes(hipStream_t s, const Ell &e);
 hipError_t launch_neumann_update(hipStream_t s, const Ell &e, int64_t N_int, int64_t N_neu, const double *wself,
-                                 const double *g, double *u_cur, double *u_next, double *nb);
+                                 const double *g, double *u_cur, double *u_next, double *nb, bool direct);
 hipError_t launch_neumann_apply(hipStream_t s, const Ell &e, int64_t N_int, int64_t N_neu, const double *wself,
                                 const double *u, double *out);
 // parity: index of the sweep within its sequence (odd sweeps run reversed when c.zigzag is set)

@@ -185,3 +185,41 @@ def test_restrictions_and_validation():
     with pytest.raises(RbfError) as ei:
         p.set_stencils(idx)
     assert ei.value.status == RBF_EINVAL
+
+
+def test_neumann_supports_with_boundary_nodes_use_two_phase_update():
+    """Imported supports where some Neumann rows also hold other Neumann
+    nodes: all new boundary values must come from the old iterate (the
+    library then evaluates into a buffer and stores in a second kernel);
+    iterates against the oracle, whose update has the same two phases."""
+    import torch
+    dim, side, m = 2, 25, 2
+    xyz, typ, normals = ri.mixed_bc_grid(dim, side, 0.3, 12)
+    n = 2 * ri.num_monomials(dim, m)
+    idx = oracle.knn(xyz, n, typ=typ)
+    neu = np.nonzero(typ == 2)[0]
+    # swap the farthest support node of every other Neumann row for the
+    # nearest other Neumann node
+    for r in neu[::2]:
+        d = ((xyz[:, neu] - xyz[:, [r]]) ** 2).sum(0)
+        d[neu == r] = np.inf
+        q = neu[np.argmin(d)]
+        if q not in idx[r]:
+            idx[r, -1] = q
+    rows = np.nonzero(typ != 1)[0]
+    op = (typ[rows] == 2).astype(np.int8)
+    w = np.zeros(idx.shape)
+    w[rows] = oracle.weights(xyz, idx[rows], rows, m=m, op_row=op, normals=normals)[0]
+    p = _problem()
+    p.set_nodes(xyz, typ)
+    p.set_normals(normals)
+    p.set_stencils(idx)
+    p.set_weights(w)
+    u_ex, f, u0 = ri.manufactured_mixed(dim, xyz, typ)
+    h = 0.5 / (side - 1)
+    dt = 0.1 * h * h / 4
+    u = torch.tensor(u0, device="cuda")
+    st, rep = p.iterate(torch.tensor(f, device="cuda"), u, dt, 2000, 0.0, 500)
+    uo, rep_o, st_o = oracle.Operator(typ, idx, w).iterate(f, dt, u0, 2000, 0.0, 500)
+    assert st == st_o == 0
+    assert np.abs(u.cpu().numpy() - uo).max() <= 1e-11 * np.abs(uo).max()

@@ -375,3 +375,50 @@ def test_zigzag_order_is_bitwise_identical(monkeypatch, steps):
             assert np.abs(out[0][0] - uo).max() <= 1e-11 * np.abs(uo).max()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+def test_codes_bitwise_identical_with_fallback_slices(monkeypatch):
+    """The sweeps read 16-bit column codes where a slice's columns fall in at
+    most 16 aligned blocks of 4096 ids, and the 32-bit ids elsewhere.  Half of
+    the rows get random far-apart supports (their slices fall back), half keep
+    their nearest-node supports; FP64 and FP32 sweeps must give the same bits
+    with and without codes, and the FP64 iterate must match the oracle."""
+    import torch
+
+    from paper_2502_12878_amd import RBF_MODE_MIXED
+    side, n = 448, 12
+    xyz, typ = ri.jittered_grid(2, side, 0.3, 16)
+    N = len(typ)
+    p = _problem()
+    p.set_nodes(xyz, typ)
+    p.build_stencils(n)
+    idx = p.get_stencils()
+    rng = np.random.default_rng(17)
+    half = np.nonzero(typ == 0)[0][: (typ == 0).sum() // 2]
+    for r in half:
+        idx[r, 1:] = rng.choice(np.setdiff1d(rng.integers(0, N, 3 * n), [r])[: n + 4], size=n - 1, replace=False)
+    w = rng.standard_normal((N, n)) * (typ == 0)[:, None]
+    f = rng.standard_normal(N) * (typ == 0)
+    u0 = rng.standard_normal(N)
+    dt = 1e-3
+    out = []
+    for cd in ("0", "1"):
+        monkeypatch.setenv("RBF_SWEEP_CODES", cd)
+        p.set_stencils(idx)
+        p.set_weights(w, keep_fp32=True)
+        info = p.operator_info()
+        assert info["f64_codes"] == int(cd) and info["f32_codes"] == int(cd)
+        assert 0 < info["coded_slices"] < info["slices"]
+        u = torch.tensor(u0, device="cuda")
+        st, rep = p.iterate(torch.tensor(f, device="cuda"), u, dt, 41, 0.0, 10)
+        assert st == 0
+        um = torch.tensor(u0, device="cuda")
+        st, _ = p.iterate(torch.tensor(f, device="cuda"), um, dt, 2 * 15, 0.0, 1, mode=RBF_MODE_MIXED, inner_steps=15)
+        assert st == 0
+        out.append((u.cpu().numpy(), um.cpu().numpy(), info))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert out[1][2]["stream_bytes_f64"] < out[0][2]["stream_bytes_f64"]
+    uo, _, st_o = oracle.Operator(typ, idx, w).iterate(f, dt, u0, 41, 0.0, 10)
+    assert st_o == 0
+    assert np.abs(out[1][0] - uo).max() <= 1e-11 * np.abs(uo).max()
