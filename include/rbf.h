@@ -264,8 +264,11 @@ rbf_status rbf_set_weights(rbf_handle *h, const double *w_host, int keep_fp32);
  * pipelining, zig-zag slice order, 16-bit column codes; weight solver: panel
  * width).  Results are cached in the JSON file named by the
  * RBF_AUTOTUNE_CACHE environment variable (none: not cached), keyed by device
- * architecture and problem shape.  RBF_SWEEP_ZIGZAG=0/1 and
- * RBF_SWEEP_CODES=0/1 fix those two choices.  Synchronises. */
+ * architecture and problem shape; a shape found there is used without timing
+ * (RBF_AUTOTUNE_FORCE=1 times again and replaces it).  RBF_SWEEP_ZIGZAG=0/1
+ * and RBF_SWEEP_CODES=0/1 fix those two choices; RBF_SWEEP_SHAPE="waves,
+ * unroll,xcd_remap,pipeline,zigzag,codes" fixes the whole sweep shape and
+ * turns the sweep timing off.  Synchronises. */
 rbf_status rbf_autotune(rbf_handle *h);
 
 /* Layout of the packed interior operator and the sweep shapes in use.

@@ -619,6 +619,24 @@ static rbf_status make_ell(rbf_handle *h, int64_t row0, int64_t nrows, const std
     return RBF_OK;
 }
 
+// Autotuner cache key of the sweep shape for the current operator (prec 0:
+// FP64 sweeps, 1: FP32).
+static void sweep_key(const rbf_handle *h, int prec, char *key, size_t len) {
+    const Ell &e = h->ell;
+    std::snprintf(key, len, "%s|%s|L%d|%" PRId64 "|%" PRId64 "|%d|c%" PRId64, prec ? "sweep32" : "sweep", h->arch,
+                  e.layout, h->N_int, e.elems, e.max_len, e.coded_slices);
+}
+
+// Apply cached shape values v[6] to c.
+static void apply_shape(SweepCfg &c, const int *v, const Ell &e) {
+    c.waves_per_block = v[0];
+    c.unroll = v[1];
+    c.xcd_remap = v[2];
+    c.pipeline = e.layout ? v[3] : 0;
+    c.zigzag = v[4];
+    c.codes = e.cmode ? v[5] : 0;
+}
+
 // RBF_SWEEP_ZIGZAG=0/1 fixes the sweep order (forward only / alternating) and
 // RBF_SWEEP_CODES=0/1 whether the sweeps read the 16-bit codes; unset, the
 // autotuner chooses.  -1 when unset.
@@ -629,6 +647,23 @@ static int env_flag(const char *name) {
 }
 static int zigzag_override() { return env_flag("RBF_SWEEP_ZIGZAG"); }
 static int codes_override() { return env_flag("RBF_SWEEP_CODES"); }
+
+// RBF_SWEEP_SHAPE="waves,unroll,xcd_remap,pipeline,zigzag,codes" fixes the
+// whole sweep shape (both precisions) and turns the sweep autotuner off.
+static bool shape_override(SweepCfg *c) {
+    const char *z = std::getenv("RBF_SWEEP_SHAPE");
+    if (!z || !z[0]) return false;
+    int v[6];
+    if (std::sscanf(z, "%d,%d,%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) != 6) return false;
+    if ((v[0] != 2 && v[0] != 4 && v[0] != 8) || (v[1] != 4 && v[1] != 8 && v[1] != 16)) return false;
+    c->waves_per_block = v[0];
+    c->unroll = v[1];
+    c->xcd_remap = v[2] != 0;
+    c->pipeline = v[3] != 0;
+    c->zigzag = v[4] != 0;
+    c->codes = v[5] != 0;
+    return true;
+}
 
 // Internal order: interior rows by descending support size then canonical id,
 // then Neumann rows likewise, then Dirichlet rows by canonical id.
@@ -704,21 +739,19 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
     char key[160];
     int v[6];
     for (int prec = 0; prec < 2; ++prec) {
-        std::snprintf(key, sizeof key, "%s|%s|L%d|%" PRId64 "|%" PRId64 "|%d|c%" PRId64, prec ? "sweep32" : "sweep",
-                      h->arch, e.layout, N_int, e.elems, e.max_len, e.coded_slices);
-        if (!cache_lookup(key, v, 6)) continue;
-        SweepCfg &c = prec ? h->cfg32 : h->cfg;
-        c.waves_per_block = v[0];
-        c.unroll = v[1];
-        c.xcd_remap = v[2];
-        c.pipeline = e.layout ? v[3] : 0;
-        c.zigzag = v[4];
-        c.codes = e.cmode ? v[5] : 0;
+        sweep_key(h, prec, key, sizeof key);
+        if (cache_lookup(key, v, 6)) apply_shape(prec ? h->cfg32 : h->cfg, v, e);
     }
     const int zz = zigzag_override();
     if (zz >= 0) h->cfg.zigzag = h->cfg32.zigzag = zz;
     const int cd = codes_override();
     if (cd >= 0) h->cfg.codes = h->cfg32.codes = (cd && e.cmode) ? 1 : 0;
+    SweepCfg forced;
+    if (shape_override(&forced)) {
+        if (!e.layout) forced.pipeline = 0;
+        if (!e.cmode) forced.codes = 0;
+        h->cfg = h->cfg32 = forced;
+    }
     return RBF_OK;
 }
 
@@ -1473,7 +1506,17 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
     HIPCHK(h, launch_fill_f64(h->stream, h->N, 0.0, h->fint));
     HIPCHK(h, launch_fill_f32(h->stream, h->N, 0.0f, h->r32));
     const int reps = 20;
-    for (int prec = 0; prec < (h->have_w32 ? 2 : 1); ++prec) {
+    SweepCfg forced;
+    const int nprec = shape_override(&forced) ? 0 : (h->have_w32 ? 2 : 1);
+    const bool force = env_flag("RBF_AUTOTUNE_FORCE") == 1;
+    for (int prec = 0; prec < nprec; ++prec) {
+        char key[160];
+        sweep_key(h, prec, key, sizeof key);
+        int cached[6];
+        if (!force && cache_lookup(key, cached, 6)) {  // tuned before for this shape
+            apply_shape(prec ? h->cfg32 : h->cfg, cached, h->ell);
+            continue;
+        }
         float best = 1e30f;
         SweepCfg bestc = prec ? h->cfg32 : h->cfg;
         auto launch = [&](const SweepCfg &c, int r) -> hipError_t {
@@ -1491,8 +1534,7 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
                     for (int cd : {0, 1}) {
                         if (pl && h->ell.layout == 0) continue;
                         if (zigzag_override() >= 0 && zz != zigzag_override()) continue;
-                        // codes are read by the plain paired loop only
-                        if (cd && (pl || !h->ell.cmode)) continue;
+                        if (cd && !h->ell.cmode) continue;
                         if (codes_override() >= 0 && cd != codes_override() && h->ell.cmode) continue;
                         SweepCfg c;
                         c.waves_per_block = wv;
@@ -1514,9 +1556,6 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
                         }
                     }
         (prec ? h->cfg32 : h->cfg) = bestc;
-        char key[160];
-        std::snprintf(key, sizeof key, "%s|%s|L%d|%" PRId64 "|%" PRId64 "|%d|c%" PRId64, prec ? "sweep32" : "sweep",
-                      h->arch, h->ell.layout, Ni, h->ell.elems, h->ell.max_len, h->ell.coded_slices);
         int v[6] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap, bestc.pipeline, bestc.zigzag, bestc.codes};
         cache_store(key, v, 6);
     }

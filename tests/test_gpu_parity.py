@@ -422,3 +422,35 @@ def test_codes_bitwise_identical_with_fallback_slices(monkeypatch):
     uo, _, st_o = oracle.Operator(typ, idx, w).iterate(f, dt, u0, 41, 0.0, 10)
     assert st_o == 0
     assert np.abs(out[1][0] - uo).max() <= 1e-11 * np.abs(uo).max()
+
+
+SHAPES = ["2,4,0,0,0,0", "8,16,1,1,1,0", "4,16,1,0,0,1", "4,8,0,1,1,1", "2,16,1,1,0,1", "8,4,0,0,1,1"]
+
+
+def test_sweep_shapes_bitwise_identical(monkeypatch):
+    """Every sweep shape (workgroup size, unroll, XCD order, pipelining,
+    zig-zag, codes) computes each row's sum in the same order: FP64 and FP32
+    iterates are bitwise equal across shapes and match the oracle."""
+    from paper_2502_12878_amd import RBF_MODE_MIXED
+    res = []
+    for shape in SHAPES:
+        monkeypatch.setenv("RBF_SWEEP_SHAPE", shape)
+        s = _setup_pair(3, 14, 4, 70, 18, keep_fp32=True)
+        info = s["p"].operator_info()
+        want = [int(x) for x in shape.split(",")]
+        got = [info[f"f64_{k}"] for k in ("waves", "unroll", "xcd_remap", "pipeline", "zigzag", "codes")]
+        assert got == want
+        s["p"].autotune()  # a fixed shape turns the sweep tuner off
+        info = s["p"].operator_info()
+        assert [info[f"f64_{k}"] for k in ("waves", "unroll", "xcd_remap", "pipeline", "zigzag", "codes")] == want
+        u = s["dev"](s["u0"])
+        st, _ = s["p"].iterate(s["dev"](s["f"]), u, s["dt"], 333, 0.0, 111)
+        assert st == 0
+        um = s["dev"](s["u0"])
+        st, _ = s["p"].iterate(s["dev"](s["f"]), um, s["dt"], 2 * 101, 0.0, 1, mode=RBF_MODE_MIXED, inner_steps=101)
+        assert st == 0
+        res.append((u.cpu().numpy(), um.cpu().numpy()))
+    for a in res[1:]:
+        assert np.array_equal(a[0], res[0][0]) and np.array_equal(a[1], res[0][1])
+    uo, _, _ = s["op"].iterate(s["f"], s["dt"], s["u0"], 333, 0.0, 111)
+    assert np.abs(res[0][0] - uo).max() <= 1e-11 * np.abs(uo).max()
