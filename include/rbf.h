@@ -249,12 +249,14 @@ rbf_status rbf_get_stencils(rbf_handle *h, int32_t *idx_host);
  * Dirichlet rows.  Synchronises. */
 rbf_status rbf_get_weights(rbf_handle *h, double *w_host);
 /* Replace the stencils: [N][n_max] int32 canonical ids, -1 padding after the
- * first n_r entries (n_r >= 1).  Clears weights.  EINVAL: ids out of range.
- * Synchronises. */
+ * first n_r entries (n_r >= 1).  Clears weights.  EINVAL: ids out of range,
+ * an id repeated within a row, padding not -1.  Synchronises. */
 rbf_status rbf_set_stencils(rbf_handle *h, const int32_t *idx_host, int32_t n_max);
 /* Replace the weights ([N][n_max] doubles in stencil order; Dirichlet rows
- * ignored) and pack the operator; keep_fp32 as in rbf_compute_weights.
- * Synchronises. */
+ * ignored; Neumann rows are normal-derivative weights) and pack the
+ * operator; keep_fp32 as in rbf_compute_weights.  EINVAL (and no operator)
+ * when a Neumann row lacks its own node or its own weight is 0 or not
+ * finite.  Synchronises. */
 rbf_status rbf_set_weights(rbf_handle *h, const double *w_host, int keep_fp32);
 
 /* ------------------------------------------------------------ tuning */

@@ -23,7 +23,7 @@ namespace {
 template <int WAVES, int U, int LAYOUT, bool REDUCE>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
-    const double *__restrict__ w, Codes cs, int64_t nslices, int64_t N_int, const double *__restrict__ f,
+    const double *__restrict__ w, Codes cs, int64_t nslices, int64_t N_int, int64_t ncols, const double *__restrict__ f,
     const double *__restrict__ u_old, double *__restrict__ u_new, double dt, unsigned long long *res_slot,
     int order) {
     const int64_t slice = slice_index<WAVES>(nslices, order);
@@ -31,7 +31,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
     unsigned long long bits = 0;
     if (slice < nslices) {
         const int len = slice_len[slice];
-        const double acc = row_dot<double, U, LAYOUT>(cs, slice_ptr, idx, w, u_old, slice, lane, len);
+        const double acc = row_dot<double, U, LAYOUT>(cs, slice_ptr, idx, w, BufGather<double>(u_old, ncols), slice, lane, len);
         const int64_t row = slice * kSlice + lane;
         if (row < N_int) {
             const double rho = acc - f[row];
@@ -46,13 +46,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
 template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep_f32(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
-    const float *__restrict__ w, Codes cs, int64_t nslices, int64_t N_int, const float *__restrict__ r,
+    const float *__restrict__ w, Codes cs, int64_t nslices, int64_t N_int, int64_t ncols, const float *__restrict__ r,
     const float *__restrict__ e_old, float *__restrict__ e_new, float dt, int order) {
     const int64_t slice = slice_index<WAVES>(nslices, order);
     const int lane = threadIdx.x & 63;
     if (slice >= nslices) return;
     const int len = slice_len[slice];
-    const float acc = row_dot<float, U, LAYOUT>(cs, slice_ptr, idx, w, e_old, slice, lane, len);
+    const float acc = row_dot<float, U, LAYOUT>(cs, slice_ptr, idx, w, BufGather<float>(e_old, ncols), slice, lane, len);
     const int64_t row = slice * kSlice + lane;
     if (row < N_int) e_new[row] = e_old[row] + dt * (acc - r[row]);
 }
@@ -61,14 +61,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f32(
 template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_apply_f64(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
-    const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ u,
+    const double *__restrict__ w, int64_t nslices, int64_t N_int, int64_t ncols, const double *__restrict__ u,
     double *__restrict__ Lu, const double *__restrict__ f, unsigned long long *res_slot, int order) {
     const int64_t slice = slice_index<WAVES>(nslices, order);
     const int lane = threadIdx.x & 63;
     unsigned long long bits = 0;
     if (slice < nslices) {
         const int len = slice_len[slice];
-        const double acc = RowDot<double, U, LAYOUT>::run(idx, w, u, slice_ptr[slice], lane, len);
+        const double acc = RowDot<double, U, LAYOUT>::run(idx, w, BufGather<double>(u, ncols), slice_ptr[slice], lane, len);
         const int64_t row = slice * kSlice + lane;
         if (row < N_int) {
             if (Lu) Lu[row] = acc;
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_apply_f64(
 template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_outer_residual(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
-    const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ f,
+    const double *__restrict__ w, int64_t nslices, int64_t N_int, int64_t ncols, const double *__restrict__ f,
     const double *__restrict__ u, float *__restrict__ r32, float *__restrict__ e0, unsigned long long *res_slot,
     int order) {
     const int64_t slice = slice_index<WAVES>(nslices, order);
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_outer_residual(
     unsigned long long bits = 0;
     if (slice < nslices) {
         const int len = slice_len[slice];
-        const double acc = RowDot<double, U, LAYOUT>::run(idx, w, u, slice_ptr[slice], lane, len);
+        const double acc = RowDot<double, U, LAYOUT>::run(idx, w, BufGather<double>(u, ncols), slice_ptr[slice], lane, len);
         const int64_t row = slice * kSlice + lane;
         if (row < N_int) {
             const double r = f[row] - acc;
@@ -108,13 +108,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_outer_residual(
 template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_adjoint_gather(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
-    const double *__restrict__ w, int64_t nslices, int64_t N_int, const double *__restrict__ lam_old,
+    const double *__restrict__ w, int64_t nslices, int64_t N_int, int64_t ncols, const double *__restrict__ lam_old,
     double *__restrict__ lam_new, double *__restrict__ acc, double dt, int order) {
     const int64_t slice = slice_index<WAVES>(nslices, order);
     const int lane = threadIdx.x & 63;
     if (slice >= nslices) return;
     const int len = slice_len[slice];
-    const double s = RowDot<double, U, LAYOUT>::run(idx, w, lam_old, slice_ptr[slice], lane, len);
+    const double s = RowDot<double, U, LAYOUT>::run(idx, w, BufGather<double>(lam_old, ncols), slice_ptr[slice], lane, len);
     const int64_t row = slice * kSlice + lane;
     if (row < N_int) {
         const double l = lam_old[row] + dt * s;
@@ -165,10 +165,10 @@ struct SweepF64 {
         const Codes cs = codes_of(e);
         if (slot)
             hipLaunchKernelGGL((k_sweep_f64<WV, UN, LY, true>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr,
-                               e.slice_len, e.idx, e.w, cs, e.nslices, N_int, f, uo, un, dt, slot, remap);
+                               e.slice_len, e.idx, e.w, cs, e.nslices, N_int, e.ncols, f, uo, un, dt, slot, remap);
         else
             hipLaunchKernelGGL((k_sweep_f64<WV, UN, LY, false>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr,
-                               e.slice_len, e.idx, e.w, cs, e.nslices, N_int, f, uo, un, dt, slot, remap);
+                               e.slice_len, e.idx, e.w, cs, e.nslices, N_int, e.ncols, f, uo, un, dt, slot, remap);
         return hipGetLastError();
     }
 };
@@ -179,7 +179,7 @@ struct SweepF32 {
                           float dt, int remap) {
         if (!e.nslices) return hipSuccess;
         hipLaunchKernelGGL((k_sweep_f32<WV, UN, LY>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
-                           e.slice_ptr, e.slice_len, e.idx, e.w32, codes_of(e), e.nslices, N_int, r, eo, en, dt,
+                           e.slice_ptr, e.slice_len, e.idx, e.w32, codes_of(e), e.nslices, N_int, e.ncols, r, eo, en, dt,
                            remap);
         return hipGetLastError();
     }
@@ -191,7 +191,7 @@ struct ApplyF64 {
                           unsigned long long *slot, int remap) {
         if (!e.nslices) return hipSuccess;
         hipLaunchKernelGGL((k_apply_f64<WV, UN, LY>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
-                           e.slice_ptr, e.slice_len, e.idx, e.w, e.nslices, N_int, u, Lu, f, slot, remap);
+                           e.slice_ptr, e.slice_len, e.idx, e.w, e.nslices, N_int, e.ncols, u, Lu, f, slot, remap);
         return hipGetLastError();
     }
 };
@@ -202,7 +202,7 @@ struct AdjGather {
                           double dt, int remap) {
         if (!e.nslices) return hipSuccess;
         hipLaunchKernelGGL((k_adjoint_gather<WV, UN, LY>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
-                           e.slice_ptr, e.slice_len, e.idx, e.w, e.nslices, N_int, lo, ln, acc, dt, remap);
+                           e.slice_ptr, e.slice_len, e.idx, e.w, e.nslices, N_int, e.ncols, lo, ln, acc, dt, remap);
         return hipGetLastError();
     }
 };
@@ -213,7 +213,7 @@ struct OuterRes {
                           float *e0, unsigned long long *slot, int remap) {
         if (!e.nslices) return hipSuccess;
         hipLaunchKernelGGL((k_outer_residual<WV, UN, LY>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
-                           e.slice_ptr, e.slice_len, e.idx, e.w, e.nslices, N_int, f, u, r32, e0, slot, remap);
+                           e.slice_ptr, e.slice_len, e.idx, e.w, e.nslices, N_int, e.ncols, f, u, r32, e0, slot, remap);
         return hipGetLastError();
     }
 };

@@ -563,6 +563,7 @@ static rbf_status make_ell(rbf_handle *h, int64_t row0, int64_t nrows, const std
                            int keep_fp32, Ell *out, double *wself, bool with_codes, int32_t *foreign = nullptr) {
     Ell e;
     e.layout = layout;
+    e.ncols = h->N;
     e.nslices = (nrows + kSlice - 1) / kSlice;
     std::vector<int64_t> sptr((size_t)e.nslices + 1);
     std::vector<int32_t> slen((size_t)e.nslices);
@@ -1006,6 +1007,7 @@ static rbf_status build_transpose(rbf_handle *h) {
     const int64_t nnz = st[Ni];
     Ell e;
     e.layout = 1;
+    e.ncols = N;
     e.nslices = (Ni + kSlice - 1) / kSlice;
     std::vector<int64_t> sptr((size_t)e.nslices + 1);
     std::vector<int32_t> slen((size_t)e.nslices);

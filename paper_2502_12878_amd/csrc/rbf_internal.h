@@ -50,6 +50,7 @@ struct Ell {
     int layout = 1;                // 0: one element per lane per entry; 1: entry pairs as vectors (k_sweep.hip)
     int64_t nslices = 0;
     int64_t elems = 0;
+    int64_t ncols = 0;             // length of the gathered vector (all nodes)
     int32_t max_len = 0;
     int64_t *slice_ptr = nullptr;  // [nslices + 1]
     int32_t *slice_len = nullptr;  // [nslices]

@@ -83,11 +83,44 @@ struct Vec2<double> { typedef f64x2 type; };
 template <>
 struct Vec2<float> { typedef f32x2 type; };
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Gathers of the iterate through a raw buffer resource: one 32-bit byte
+// offset per lane (no 64-bit address arithmetic, half the address
+// registers), and an offset past the n elements reads 0 instead of faulting.
+template <typename T>
+struct BufGather;
+template <>
+struct BufGather<double> {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ BufGather(const double *p, int64_t n) {
+        const uint64_t bytes = (uint64_t)n * 8u;
+        r = __builtin_amdgcn_make_buffer_rsrc((void *)p, 0, (int)(bytes > 0xffffffffu ? 0xffffffffu : bytes),
+                                              0x00020000);
+    }
+    __device__ __forceinline__ double operator[](int32_t j) const {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (uint32_t)j * 8u, 0, 0));
+    }
+};
+template <>
+struct BufGather<float> {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ BufGather(const float *p, int64_t n) {
+        const uint64_t bytes = (uint64_t)n * 4u;
+        r = __builtin_amdgcn_make_buffer_rsrc((void *)p, 0, (int)(bytes > 0xffffffffu ? 0xffffffffu : bytes),
+                                              0x00020000);
+    }
+    __device__ __forceinline__ float operator[](int32_t j) const {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (uint32_t)j * 4u, 0, 0));
+    }
+};
+
 // sum_k w[k] * x[idx[k]] over one row's packed entries (k < len), layout 0.
 template <typename T, int U, int LAYOUT>
 struct RowDot {
-    __device__ static __forceinline__ T run(const int32_t *__restrict__ idx, const T *__restrict__ w,
-                                            const T *__restrict__ x, int64_t base, int lane, int len) {
+    template <class X>
+    __device__ static __forceinline__ T run(const int32_t *__restrict__ idx, const T *__restrict__ w, const X &x,
+                                            int64_t base, int lane, int len) {
         T acc = T(0);
         int k = 0;
         base += lane;
@@ -117,8 +150,9 @@ struct RowDot {
 // Layout 1: pairs of entries as vectors; len is even.
 template <typename T, int U>
 struct RowDot<T, U, 1> {
-    __device__ static __forceinline__ T run(const int32_t *__restrict__ idx, const T *__restrict__ w,
-                                            const T *__restrict__ x, int64_t base, int lane, int len) {
+    template <class X>
+    __device__ static __forceinline__ T run(const int32_t *__restrict__ idx, const T *__restrict__ w, const X &x,
+                                            int64_t base, int lane, int len) {
         typedef typename Vec2<T>::type V;
         constexpr int P = U / 2;
         T acc = T(0);
@@ -160,8 +194,9 @@ struct RowDot<T, U, 1> {
 // wavefront keeps two groups of stream loads in flight.
 template <typename T, int U>
 struct RowDot<T, U, 2> {
-    __device__ static __forceinline__ T run(const int32_t *__restrict__ idx, const T *__restrict__ w,
-                                            const T *__restrict__ x, int64_t base, int lane, int len) {
+    template <class X>
+    __device__ static __forceinline__ T run(const int32_t *__restrict__ idx, const T *__restrict__ w, const X &x,
+                                            int64_t base, int lane, int len) {
         typedef typename Vec2<T>::type V;
         constexpr int P = U / 2;
         T acc = T(0);
@@ -227,8 +262,9 @@ __device__ __forceinline__ int32_t code_col(uint32_t c, int32_t segreg) {
 template <typename T, int U>
 struct RowDotC {
     static_assert(U % 4 == 0, "groups of whole code vectors");
+    template <class X>
     __device__ static __forceinline__ T run(const uint16_t *__restrict__ code, int32_t segreg,
-                                            const T *__restrict__ w, const T *__restrict__ x, int lane, int len) {
+                                            const T *__restrict__ w, const X &x, int lane, int len) {
         typedef typename Vec2<T>::type V;
         T acc = T(0);
         const u16x4 *cp = (const u16x4 *)code + lane;
@@ -271,8 +307,9 @@ struct RowDotC {
 template <typename T, int U>
 struct RowDotCP {
     static_assert(U % 4 == 0, "groups of whole code vectors");
+    template <class X>
     __device__ static __forceinline__ T run(const uint16_t *__restrict__ code, int32_t segreg,
-                                            const T *__restrict__ w, const T *__restrict__ x, int lane, int len) {
+                                            const T *__restrict__ w, const X &x, int lane, int len) {
         typedef typename Vec2<T>::type V;
         T acc = T(0);
         const u16x4 *cp = (const u16x4 *)code + lane;
@@ -338,10 +375,10 @@ struct Codes {
 // LAYOUT 3 / 4 are layouts 1 / 2 read through the codes (kernels compiled
 // for them hold both loops; the others hold only their own, which keeps their
 // registers).
-template <typename T, int U, int LAYOUT>
+template <typename T, int U, int LAYOUT, class X>
 __device__ __forceinline__ T row_dot(const Codes &cs, const int64_t *__restrict__ slice_ptr,
-                                     const int32_t *__restrict__ idx, const T *__restrict__ w,
-                                     const T *__restrict__ x, int64_t slice, int lane, int len) {
+                                     const int32_t *__restrict__ idx, const T *__restrict__ w, const X &x,
+                                     int64_t slice, int lane, int len) {
     if constexpr (LAYOUT == 3 || LAYOUT == 4) {
         if (cs.cmode[slice]) {
             const int32_t segreg = cs.segbase[slice * kSegs + (lane & (kSegs - 1))];

@@ -67,15 +67,33 @@ def test_create_without_device_fails_cleanly(lib):
     assert not h.value
 
 
+_CTYPES = {"double": C.c_double, "int64_t": C.c_int64, "int32_t": C.c_int32, "const double *": C.c_void_p}
+
+
 def test_iter_struct_layout_matches_header():
-    """Field order and sizes of the two structs as the header declares them."""
+    """Field order and types of the ABI structs as the header declares them
+    (comma-separated declarators included)."""
     from paper_2502_12878_amd import _abi
     text = open(HEADER).read()
-    for cls, cname in ((_abi.rbf_iter_params, "rbf_iter_params"), (_abi.rbf_iter_report, "rbf_iter_report")):
+    for cls, cname in ((_abi.rbf_iter_params, "rbf_iter_params"), (_abi.rbf_iter_report, "rbf_iter_report"),
+                       (_abi.rbf_operator_info, "rbf_operator_info")):
         body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + ";", text).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-        fields = re.findall(r"\b(\w+)\s*;", body)
-        assert [f for f, _ in cls._fields_] == [f.replace("*", "") for f in fields]
+        fields = []
+        for decl in body.split(";"):
+            decl = " ".join(decl.split())
+            if not decl:
+                continue
+            m = re.match(r"((?:const\s+)?\w+\s*\*?)\s*(.*)", decl)
+            ctype = m.group(1).replace(" *", " *").strip()
+            for name in m.group(2).split(","):
+                name = name.strip().lstrip("*")
+                if "*" in m.group(1):
+                    ctype = "const double *"
+                fields.append((name, ctype))
+        assert [f for f, _ in cls._fields_] == [f for f, _ in fields], cname
+        for (f, t), (_, ct) in zip(cls._fields_, fields):
+            assert C.sizeof(t) == C.sizeof(_CTYPES[ct]), (cname, f)
 
 
 def test_package_import_does_not_need_a_gpu():
