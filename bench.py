@@ -35,16 +35,16 @@ def sweep_source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(key):
+def stored_traffic(key, shape):
     """HBM bytes per sweep launch measured with rocprofv3 counters, if they
-    were taken on the current sweep source; else None."""
+    were taken on the current sweep source in the same sweep shape; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
     e = d.get(key)
-    if not e or e.get("kernel_source") != sweep_source_hash():
+    if not e or e.get("kernel_source") != sweep_source_hash() or e.get("shape") != shape:
         return None
     return e.get("bytes_per_launch")
 
@@ -621,7 +621,9 @@ def main():
     s, entry, wall, per_sweep, nsw = head
     wl = s["wl"]
     key = f"sweep_f64|cube1M|m{wl.m}"
-    traffic = stored_traffic(key)
+    sh = entry["sweep_shape"]
+    traffic = stored_traffic(key, ",".join(str(sh[k]) for k in ("waves", "unroll", "xcd_remap", "pipeline",
+                                                                "zigzag", "codes")))
     alg_bytes = entry["alg_bytes_per_update"] * entry["interior_nodes"]
     roofline = {"bound": "hbm", "achieved": round(alg_bytes / per_sweep / 1e9, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(alg_bytes / per_sweep / 1e9 / PEAK_HBM_GBS, 4),
@@ -630,6 +632,10 @@ def main():
                 "format_bytes_per_launch": entry["format_bytes_per_sweep"],
                 "format_frac": round(entry["format_GBps"] / PEAK_HBM_GBS, 4), "sweep_shape": entry["sweep_shape"]}
     tte = None if args.no_tte else time_to_error(s, args.tte_target)
+    if tte is not None:
+        info = s["p"].operator_info()
+        tte["fp32_sweep_shape"] = {k[4:]: v for k, v in info.items() if k.startswith("f32_")}
+        tte["fp32_format_bytes_per_sweep"] = info["stream_bytes_f32"]
     cpu = None if args.no_cpu else cpu_baseline()
     out = {"metric": "sweep node-updates/s + HBM GB/s; time to L-inf err 1e-6, FP32+refine vs FP64",
            "value": entry["node_updates_per_s"], "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps,
