@@ -263,14 +263,14 @@ rbf_status rbf_set_weights(rbf_handle *h, const double *w_host, int keep_fp32);
 
 /* Time candidate kernel shapes for the current operator and keep the fastest
  * (sweep: rows per workgroup, unroll depth, XCD-aware block order, software
- * pipelining, zig-zag slice order, 16-bit column codes; weight solver: panel
- * width).  Results are cached in the JSON file named by the
+ * pipelining, zig-zag slice order, 16-bit column codes, non-temporal or
+ * ordinary operator loads; weight solver: panel width).  Results are cached in the JSON file named by the
  * RBF_AUTOTUNE_CACHE environment variable (none: not cached), keyed by device
  * architecture and problem shape; a shape found there is used without timing
  * (RBF_AUTOTUNE_FORCE=1 times again and replaces it).  RBF_SWEEP_ZIGZAG=0/1
  * and RBF_SWEEP_CODES=0/1 fix those two choices; RBF_SWEEP_SHAPE="waves,
- * unroll,xcd_remap,pipeline,zigzag,codes" fixes the whole sweep shape and
- * turns the sweep timing off.  Synchronises. */
+ * unroll,xcd_remap,pipeline,zigzag,codes[,temporal]" fixes the whole sweep
+ * shape and turns the sweep timing off.  Synchronises. */
 rbf_status rbf_autotune(rbf_handle *h);
 
 /* Layout of the packed interior operator and the sweep shapes in use.
@@ -287,6 +287,7 @@ typedef struct {
     int32_t f64_waves, f64_unroll, f64_xcd_remap, f64_pipeline, f64_zigzag, f64_codes;
     int32_t f32_waves, f32_unroll, f32_xcd_remap, f32_pipeline, f32_zigzag, f32_codes;
     double stream_bytes_f64, stream_bytes_f32;
+    int32_t f64_temporal, f32_temporal;  /* code-reading sweeps: ordinary (1) or non-temporal (0) loads */
 } rbf_operator_info;
 
 /* Fill *info for the current operator (EINVAL without one). */

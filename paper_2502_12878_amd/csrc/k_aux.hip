@@ -132,46 +132,65 @@ __global__ void k_pack_ell(int64_t row0, int64_t nrows, int32_t n_max, int32_t k
 
 // Neumann update, first half: nb[j] = (g_j - sum_{k != self} w_jk u_k) / w_jj
 // for Neumann row j (internal row N_int + j), all from the current iterate.
-// The Neumann rows are few (one face layer), so each slice gets a whole
-// workgroup: wavefront q sums the q-th quarter of the slice's entries and the
-// four partial sums are added in a fixed order.  With u_cur / u_next
-// (supports of interior nodes and the row itself only, so no Neumann row
-// reads another's value) the new value goes straight into both iterate
-// buffers.  With g null, nb[N_int + j] = (D u)_j instead (the derivative).
+// The Neumann rows are few (one face layer), so each slice gets a workgroup
+// of kNeuWaves wavefronts: wavefront q sums the q-th part of the slice's
+// entries, issuing all its index and weight loads before its gathers (two
+// memory round trips for up to kNeuBatch entries), and the partial sums
+// are added in a fixed order.  With u_cur / u_next (supports of interior
+// nodes and the row itself only, so no Neumann row reads another's value)
+// the new value goes straight into both iterate buffers.  With g null,
+// nb[N_int + j] = (D u)_j instead (the derivative).
+constexpr int kNeuWaves = 8;
+constexpr int kNeuBatch = 16;
+
 template <int LAYOUT>
-__global__ __launch_bounds__(256) void k_neumann_eval(
+__global__ __launch_bounds__(kNeuWaves * 64) void k_neumann_eval(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
     const double *__restrict__ w, int64_t N_int, int64_t N_neu, const double *__restrict__ wself,
     const double *__restrict__ g, const double *u, double *__restrict__ nb, double *u_cur, double *u_next) {
-    __shared__ double part[4][kSlice];
+    __shared__ double part[kNeuWaves][kSlice];
     const int64_t slice = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int len = slice_len[slice];
     const int64_t base = slice_ptr[slice];
-    const int chunk = ((len + 7) >> 3) << 1;  // even, 4 chunks cover len
+    const int chunk = (len + kNeuWaves - 1) / kNeuWaves;
     const int k0 = min(len, wave * chunk), k1 = min(len, k0 + chunk);
     double acc = 0.0;
-#pragma unroll 4
-    for (int k = k0; k < k1; ++k) {
-        const int64_t pos = ell_pos(LAYOUT, base, k, lane);
-        acc = fma(ld_stream(w + pos), u[ld_stream(idx + pos)], acc);
+    for (int kb = k0; kb < k1; kb += kNeuBatch) {
+        int32_t j[kNeuBatch];
+        double ww[kNeuBatch];
+#pragma unroll
+        for (int q = 0; q < kNeuBatch; ++q) {
+            const bool on = kb + q < k1;
+            const int64_t pos = ell_pos(LAYOUT, base, on ? kb + q : k0, lane);
+            j[q] = ld_stream(idx + pos);
+            ww[q] = on ? ld_stream(w + pos) : 0.0;
+        }
+        double xx[kNeuBatch];
+#pragma unroll
+        for (int q = 0; q < kNeuBatch; ++q) xx[q] = u[j[q]];
+#pragma unroll
+        for (int q = 0; q < kNeuBatch; ++q)
+            if (kb + q < k1) acc = fma(ww[q], xx[q], acc);
     }
     part[wave][lane] = acc;
     __syncthreads();
     if (wave) return;
-    acc = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
-    const int64_t j = slice * kSlice + lane;
-    if (j >= N_neu) return;
+    acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNeuWaves; ++q) acc += part[q][lane];
+    const int64_t jr = slice * kSlice + lane;
+    if (jr >= N_neu) return;
     if (g) {
-        const double v = (g[N_int + j] - acc) / wself[j];
+        const double v = (g[N_int + jr] - acc) / wself[jr];
         if (u_cur) {
-            u_cur[N_int + j] = v;
-            u_next[N_int + j] = v;
+            u_cur[N_int + jr] = v;
+            u_next[N_int + jr] = v;
         } else {
-            nb[j] = v;
+            nb[jr] = v;
         }
     } else {
-        nb[N_int + j] = acc + wself[j] * u[N_int + j];
+        nb[N_int + jr] = acc + wself[jr] * u[N_int + jr];
     }
 }
 
@@ -296,10 +315,10 @@ hipError_t launch_neumann_update(hipStream_t s, const Ell &e, int64_t N_int, int
     const dim3 grid((unsigned)e.nslices);
     double *uc = direct ? u_cur : nullptr, *un = direct ? u_next : nullptr;
     if (e.layout)
-        hipLaunchKernelGGL(k_neumann_eval<1>, grid, dim3(256), 0, s, e.slice_ptr, e.slice_len, e.idx, e.w, N_int,
+        hipLaunchKernelGGL(k_neumann_eval<1>, grid, dim3(kNeuWaves * 64), 0, s, e.slice_ptr, e.slice_len, e.idx, e.w, N_int,
                            N_neu, wself, g, u_cur, nb, uc, un);
     else
-        hipLaunchKernelGGL(k_neumann_eval<0>, grid, dim3(256), 0, s, e.slice_ptr, e.slice_len, e.idx, e.w, N_int,
+        hipLaunchKernelGGL(k_neumann_eval<0>, grid, dim3(kNeuWaves * 64), 0, s, e.slice_ptr, e.slice_len, e.idx, e.w, N_int,
                            N_neu, wself, g, u_cur, nb, uc, un);
     if (!direct)
         hipLaunchKernelGGL(k_neumann_store, dim3(grid1d(N_neu, 256)), dim3(256), 0, s, N_int, N_neu, nb, u_cur,
@@ -313,10 +332,10 @@ hipError_t launch_neumann_apply(hipStream_t s, const Ell &e, int64_t N_int, int6
     if (!e.nslices) return hipSuccess;
     const dim3 grid((unsigned)e.nslices);
     if (e.layout)
-        hipLaunchKernelGGL(k_neumann_eval<1>, grid, dim3(256), 0, s, e.slice_ptr, e.slice_len, e.idx, e.w, N_int,
+        hipLaunchKernelGGL(k_neumann_eval<1>, grid, dim3(kNeuWaves * 64), 0, s, e.slice_ptr, e.slice_len, e.idx, e.w, N_int,
                            N_neu, wself, nullptr, u, out, nullptr, nullptr);
     else
-        hipLaunchKernelGGL(k_neumann_eval<0>, grid, dim3(256), 0, s, e.slice_ptr, e.slice_len, e.idx, e.w, N_int,
+        hipLaunchKernelGGL(k_neumann_eval<0>, grid, dim3(kNeuWaves * 64), 0, s, e.slice_ptr, e.slice_len, e.idx, e.w, N_int,
                            N_neu, wself, nullptr, u, out, nullptr, nullptr);
     return hipGetLastError();
 }

@@ -108,13 +108,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_outer_residual(
 template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_adjoint_gather(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
-    const double *__restrict__ w, int64_t nslices, int64_t N_int, int64_t ncols, const double *__restrict__ lam_old,
-    double *__restrict__ lam_new, double *__restrict__ acc, double dt, int order) {
+    const double *__restrict__ w, Codes cs, int64_t nslices, int64_t N_int, int64_t ncols,
+    const double *__restrict__ lam_old, double *__restrict__ lam_new, double *__restrict__ acc, double dt, int order) {
     const int64_t slice = slice_index<WAVES>(nslices, order);
     const int lane = threadIdx.x & 63;
     if (slice >= nslices) return;
     const int len = slice_len[slice];
-    const double s = RowDot<double, U, LAYOUT>::run(idx, w, BufGather<double>(lam_old, ncols), slice_ptr[slice], lane, len);
+    const double s =
+        row_dot<double, U, LAYOUT>(cs, slice_ptr, idx, w, BufGather<double>(lam_old, ncols), slice, lane, len);
     const int64_t row = slice * kSlice + lane;
     if (row < N_int) {
         const double l = lam_old[row] + dt * s;
@@ -139,11 +140,14 @@ hipError_t dispatch_shape(const SweepCfg &c, int layout, A &&...a) {
     return hipErrorInvalidValue;
 }
 
-// The same over the shapes of the sweeps that read codes (LAYOUT 3).
+// The same over the shapes of the sweeps that read codes (LAYOUT 3 to 6).
 template <template <int, int, int> class F, typename... A>
 hipError_t dispatch_codes(const SweepCfg &c, A &&...a) {
 #define RBF_CASE(WV, UN) \
-    if (c.waves_per_block == WV && c.unroll == UN) return c.pipeline ? F<WV, UN, 4>::run(a...) : F<WV, UN, 3>::run(a...);
+    if (c.waves_per_block == WV && c.unroll == UN) {                                                \
+        if (c.temporal) return c.pipeline ? F<WV, UN, 6>::run(a...) : F<WV, UN, 5>::run(a...);      \
+        return c.pipeline ? F<WV, UN, 4>::run(a...) : F<WV, UN, 3>::run(a...);                       \
+    }
     RBF_CASE(2, 4) RBF_CASE(2, 8) RBF_CASE(2, 16)
     RBF_CASE(4, 4) RBF_CASE(4, 8) RBF_CASE(4, 16)
     RBF_CASE(8, 4) RBF_CASE(8, 8) RBF_CASE(8, 16)
@@ -202,7 +206,8 @@ struct AdjGather {
                           double dt, int remap) {
         if (!e.nslices) return hipSuccess;
         hipLaunchKernelGGL((k_adjoint_gather<WV, UN, LY>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
-                           e.slice_ptr, e.slice_len, e.idx, e.w, e.nslices, N_int, e.ncols, lo, ln, acc, dt, remap);
+                           e.slice_ptr, e.slice_len, e.idx, e.w, codes_of(e), e.nslices, N_int, e.ncols, lo, ln, acc,
+                           dt, remap);
         return hipGetLastError();
     }
 };
@@ -249,6 +254,8 @@ hipError_t launch_outer_residual(hipStream_t s, const SweepCfg &c, const Ell &e,
 
 hipError_t launch_adjoint_gather(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *lam_old,
                                  double *lam_new, double *acc, double dt, int parity) {
+    if (use_codes(c, e))
+        return dispatch_codes<AdjGather>(c, s, e, N_int, lam_old, lam_new, acc, dt, order_flags(c, parity));
     return dispatch_shape<AdjGather>(c, e.layout, s, e, N_int, lam_old, lam_new, acc, dt, order_flags(c, parity));
 }
 

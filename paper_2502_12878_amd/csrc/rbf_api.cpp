@@ -118,7 +118,13 @@ void drop_operator(rbf_handle *h) {
     free_t(h, h->ellT.slice_len);
     free_t(h, h->ellT.idx);
     free_t(h, h->ellT.w);
+    free_t(h, h->ellT.code);
+    free_t(h, h->ellT.cptr);
+    free_t(h, h->ellT.segbase);
+    free_t(h, h->ellT.cmode);
     h->ellT = Ell{};
+    h->cfgT = SweepCfg{};
+    h->tunedT = false;
     free_t(h, h->ellN.slice_ptr);
     free_t(h, h->ellN.slice_len);
     free_t(h, h->ellN.idx);
@@ -559,6 +565,30 @@ rbf_status rbf_build_stencils(rbf_handle *h, int32_t n_uniform, const int16_t *n
 // ====================================================================== packed operator
 // Sliced operator over internal rows [row0, row0 + nrows) (perm gives their
 // canonical ids); with wself, each row's own weight is split out (Neumann rows).
+// 16-bit segment codes for the column ids of a packed operator in layout 1
+// (the sweeps' index stream at half the bytes); the block number of an id
+// must fit in 16 bits.  slen: the slice lengths.  RBF_ELL_CODES=0 skips them.
+static rbf_status attach_codes(rbf_handle *h, Ell &e, const std::vector<int32_t> &slen) {
+    const char *cenv = std::getenv("RBF_ELL_CODES");
+    if (e.layout != 1 || !e.nslices || (cenv && cenv[0] == '0') || h->N >= ((int64_t)1 << 28)) return RBF_OK;
+    std::vector<int64_t> cp((size_t)e.nslices + 1);
+    cp[0] = 0;
+    for (int64_t s = 0; s < e.nslices; ++s) cp[s + 1] = cp[s] + (int64_t)kSlice * ((slen[s] + 3) & ~3);
+    e.celems = cp[e.nslices];
+    ALLOC(h, e.code, uint16_t, e.celems);
+    ALLOC(h, e.cptr, int64_t, e.nslices + 1);
+    ALLOC(h, e.segbase, int32_t, (size_t)kSegs * e.nslices);
+    ALLOC(h, e.cmode, int8_t, e.nslices);
+    HIPCHK(h, hipMemcpyAsync(e.cptr, cp.data(), sizeof(int64_t) * (e.nslices + 1), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, launch_encode_codes(h->stream, e));
+    std::vector<int8_t> cm((size_t)e.nslices);
+    HIPCHK(h, hipMemcpyAsync(cm.data(), e.cmode, (size_t)e.nslices, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    e.coded_slices = 0;
+    for (int8_t c : cm) e.coded_slices += c;
+    return RBF_OK;
+}
+
 static rbf_status make_ell(rbf_handle *h, int64_t row0, int64_t nrows, const std::vector<int32_t> &perm, int layout,
                            int keep_fp32, Ell *out, double *wself, bool with_codes, int32_t *foreign = nullptr) {
     Ell e;
@@ -594,27 +624,9 @@ static rbf_status make_ell(rbf_handle *h, int64_t row0, int64_t nrows, const std
         HIPCHK(h, launch_pack_ell(h->stream, row0, nrows, h->n_max, h->perm, h->iperm, h->sten, h->nrow, h->w_can, e,
                                   wself, foreign));
     }
-    // 16-bit segment codes for the column ids (the sweeps' index stream at half
-    // the bytes); the block number of an id must fit in 16 bits
-    const char *cenv = std::getenv("RBF_ELL_CODES");
-    const bool want_codes = with_codes && e.layout == 1 && e.nslices && !(cenv && cenv[0] == '0') &&
-                            h->N < ((int64_t)1 << 28);
-    if (want_codes) {
-        std::vector<int64_t> cp((size_t)e.nslices + 1);
-        cp[0] = 0;
-        for (int64_t s = 0; s < e.nslices; ++s) cp[s + 1] = cp[s] + (int64_t)kSlice * ((slen[s] + 3) & ~3);
-        e.celems = cp[e.nslices];
-        ALLOC(h, e.code, uint16_t, e.celems);
-        ALLOC(h, e.cptr, int64_t, e.nslices + 1);
-        ALLOC(h, e.segbase, int32_t, (size_t)kSegs * e.nslices);
-        ALLOC(h, e.cmode, int8_t, e.nslices);
-        *out = e;
-        HIPCHK(h, hipMemcpyAsync(e.cptr, cp.data(), sizeof(int64_t) * (e.nslices + 1), hipMemcpyHostToDevice, h->stream));
-        HIPCHK(h, launch_encode_codes(h->stream, e));
-        std::vector<int8_t> cm((size_t)e.nslices);
-        HIPCHK(h, hipMemcpyAsync(cm.data(), e.cmode, (size_t)e.nslices, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-        for (int8_t c : cm) e.coded_slices += c;
+    if (with_codes) {
+        const rbf_status st = attach_codes(h, e, slen);
+        if (st) return st;
         *out = e;
     }
     return RBF_OK;
@@ -628,7 +640,7 @@ static void sweep_key(const rbf_handle *h, int prec, char *key, size_t len) {
                   e.layout, h->N_int, e.elems, e.max_len, e.coded_slices);
 }
 
-// Apply cached shape values v[6] to c.
+// Apply cached shape values v[7] to c.
 static void apply_shape(SweepCfg &c, const int *v, const Ell &e) {
     c.waves_per_block = v[0];
     c.unroll = v[1];
@@ -636,6 +648,15 @@ static void apply_shape(SweepCfg &c, const int *v, const Ell &e) {
     c.pipeline = e.layout ? v[3] : 0;
     c.zigzag = v[4];
     c.codes = e.cmode ? v[5] : 0;
+    c.temporal = c.codes ? v[6] : 0;
+}
+
+// Cached shape of `key` into v[7]; entries written before the temporal-load
+// choice existed hold 6 values (temporal = 0).
+static bool lookup_shape(const char *key, int *v) {
+    if (cache_lookup(key, v, 7)) return true;
+    v[6] = 0;
+    return cache_lookup(key, v, 6);
 }
 
 // RBF_SWEEP_ZIGZAG=0/1 fixes the sweep order (forward only / alternating) and
@@ -649,13 +670,15 @@ static int env_flag(const char *name) {
 static int zigzag_override() { return env_flag("RBF_SWEEP_ZIGZAG"); }
 static int codes_override() { return env_flag("RBF_SWEEP_CODES"); }
 
-// RBF_SWEEP_SHAPE="waves,unroll,xcd_remap,pipeline,zigzag,codes" fixes the
-// whole sweep shape (both precisions) and turns the sweep autotuner off.
+// RBF_SWEEP_SHAPE="waves,unroll,xcd_remap,pipeline,zigzag,codes[,temporal]"
+// fixes the whole sweep shape (both precisions) and turns the sweep
+// autotuner off.
 static bool shape_override(SweepCfg *c) {
     const char *z = std::getenv("RBF_SWEEP_SHAPE");
     if (!z || !z[0]) return false;
-    int v[6];
-    if (std::sscanf(z, "%d,%d,%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) != 6) return false;
+    int v[7] = {0, 0, 0, 0, 0, 0, 0};
+    const int got = std::sscanf(z, "%d,%d,%d,%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6]);
+    if (got != 6 && got != 7) return false;
     if ((v[0] != 2 && v[0] != 4 && v[0] != 8) || (v[1] != 4 && v[1] != 8 && v[1] != 16)) return false;
     c->waves_per_block = v[0];
     c->unroll = v[1];
@@ -663,6 +686,7 @@ static bool shape_override(SweepCfg *c) {
     c->pipeline = v[3] != 0;
     c->zigzag = v[4] != 0;
     c->codes = v[5] != 0;
+    c->temporal = c->codes && v[6] != 0;
     return true;
 }
 
@@ -738,10 +762,10 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
     h->have_w32 = keep_fp32 != 0;
     // a tuned shape for this operator, if cached
     char key[160];
-    int v[6];
+    int v[7];
     for (int prec = 0; prec < 2; ++prec) {
         sweep_key(h, prec, key, sizeof key);
-        if (cache_lookup(key, v, 6)) apply_shape(prec ? h->cfg32 : h->cfg, v, e);
+        if (lookup_shape(key, v)) apply_shape(prec ? h->cfg32 : h->cfg, v, e);
     }
     const int zz = zigzag_override();
     if (zz >= 0) h->cfg.zigzag = h->cfg32.zigzag = zz;
@@ -1045,7 +1069,9 @@ static rbf_status build_transpose(rbf_handle *h) {
     dfree(h, rows_t);
     dfree(h, w_t);
     h->ellT = e;
-    return RBF_OK;
+    const rbf_status cst = attach_codes(h, e, slen);
+    h->ellT = e;
+    return cst;
 }
 
 static bool use_scatter_transpose() {
@@ -1149,7 +1175,7 @@ static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, d
         // ua and ub (from `start`), acc = tmp accumulates every new lam.
         double *a = start ? h->ub : h->ua, *b = start ? h->ua : h->ub;
         for (int64_t i = 0; i < steps && e == hipSuccess; ++i) {
-            e = launch_adjoint_gather(s, h->cfg, h->ellT, Ni, a, b, h->tmp, dt, (int)(i & 1));
+            e = launch_adjoint_gather(s, h->cfgT, h->ellT, Ni, a, b, h->tmp, dt, (int)(i & 1));
             std::swap(a, b);
         }
     }
@@ -1404,6 +1430,8 @@ extern "C" rbf_status rbf_get_operator_info(const rbf_handle *h, rbf_operator_in
     info->f32_pipeline = b.pipeline;
     info->f32_zigzag = b.zigzag;
     info->f32_codes = b.codes && e.cmode ? 1 : 0;
+    info->f64_temporal = info->f64_codes && a.temporal;
+    info->f32_temporal = info->f32_codes && b.temporal;
     info->stream_bytes_f64 = stream_bytes(h, 8, 8, info->f64_codes);
     info->stream_bytes_f32 = h->have_w32 ? stream_bytes(h, 4, 4, info->f32_codes) : 0.0;
     return RBF_OK;
@@ -1444,6 +1472,68 @@ extern "C" rbf_status rbf_forward_ckpt(rbf_handle *h, const double *f_dev, const
     return RBF_OK;
 }
 
+// Sweep shape of the transposed gather (its rows are the interior columns of
+// L, of uneven length): cached like the forward shapes under "sweepT|...",
+// else timed over the same candidates on the handle's work vectors.
+static rbf_status tune_transpose(rbf_handle *h) {
+    const Ell &e = h->ellT;
+    if (!e.nslices || h->tunedT) return RBF_OK;
+    char key[160];
+    std::snprintf(key, sizeof key, "sweepT|%s|L%d|%" PRId64 "|%" PRId64 "|%d|c%" PRId64, h->arch, e.layout,
+                  h->N_int, e.elems, e.max_len, e.coded_slices);
+    int v[7];
+    SweepCfg forced;
+    if (shape_override(&forced)) {
+        if (!e.cmode) forced.codes = forced.temporal = 0;
+        h->cfgT = forced;
+    } else if (env_flag("RBF_AUTOTUNE_FORCE") != 1 && lookup_shape(key, v)) {
+        apply_shape(h->cfgT, v, e);
+    } else {
+        const int64_t Ni = h->N_int;
+        HIPCHK(h, launch_fill_f64(h->stream, h->N, 0.0, h->ua));
+        HIPCHK(h, launch_fill_f64(h->stream, h->N, 0.0, h->ub));
+        HIPCHK(h, launch_fill_f64(h->stream, h->N, 0.0, h->tmp));
+        float best = 1e30f;
+        SweepCfg bestc = h->cfgT;
+        for (int wv : {2, 4, 8})
+            for (int un : {4, 8, 16})
+                for (int rm : {0, 1})
+                    for (int pl : {0, 1})
+                    for (int cd : {0, 1})
+                    for (int tp : {0, 1}) {
+                        if ((cd && !e.cmode) || (tp && !cd)) continue;
+                        SweepCfg c;
+                        c.waves_per_block = wv;
+                        c.unroll = un;
+                        c.xcd_remap = rm;
+                        c.pipeline = pl;
+                        c.codes = cd;
+                        c.temporal = tp;
+                        auto launch = [&](int r) {
+                            return launch_adjoint_gather(h->stream, c, e, Ni, (r & 1) ? h->ub : h->ua,
+                                                         (r & 1) ? h->ua : h->ub, h->tmp, 0.0, r & 1);
+                        };
+                        HIPCHK(h, launch(0));
+                        HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+                        for (int r = 0; r < 20; ++r) HIPCHK(h, launch(r));
+                        HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+                        HIPCHK(h, hipEventSynchronize(h->ev1));
+                        float ms = 0.f;
+                        HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+                        if (ms < best) {
+                            best = ms;
+                            bestc = c;
+                        }
+                    }
+        h->cfgT = bestc;
+        int vv[7] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap, bestc.pipeline, bestc.zigzag, bestc.codes,
+                     bestc.temporal};
+        cache_store(key, vv, 7);
+    }
+    h->tunedT = true;
+    return RBF_OK;
+}
+
 extern "C" rbf_status rbf_adjoint_f(rbf_handle *h, const double *gK_dev, int64_t K, int64_t every,
                                     const double *ckpt_dev, double *grad_f_dev, double dt) {
     (void)ckpt_dev;  // the gradient with respect to f does not depend on the states
@@ -1459,6 +1549,7 @@ extern "C" rbf_status rbf_adjoint_f(rbf_handle *h, const double *gK_dev, int64_t
     const bool scatter = use_scatter_transpose();
     if (!scatter) {
         rbf_status st = build_transpose(h);
+        if (!st) st = tune_transpose(h);
         if (st) return st;
     }
     // lam = gK on interior rows (0 elsewhere); acc = lam
@@ -1514,8 +1605,8 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
     for (int prec = 0; prec < nprec; ++prec) {
         char key[160];
         sweep_key(h, prec, key, sizeof key);
-        int cached[6];
-        if (!force && cache_lookup(key, cached, 6)) {  // tuned before for this shape
+        int cached[7];
+        if (!force && lookup_shape(key, cached)) {  // tuned before for this shape
             apply_shape(prec ? h->cfg32 : h->cfg, cached, h->ell);
             continue;
         }
@@ -1533,8 +1624,10 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
                 for (int rm : {0, 1})
                     for (int pl : {0, 1})
                     for (int zz : {0, 1})
-                    for (int cd : {0, 1}) {
+                    for (int cd : {0, 1})
+                    for (int tp : {0, 1}) {
                         if (pl && h->ell.layout == 0) continue;
+                        if (tp && !cd) continue;
                         if (zigzag_override() >= 0 && zz != zigzag_override()) continue;
                         if (cd && !h->ell.cmode) continue;
                         if (codes_override() >= 0 && cd != codes_override() && h->ell.cmode) continue;
@@ -1545,6 +1638,7 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
                         c.pipeline = pl;
                         c.zigzag = zz;
                         c.codes = cd;
+                        c.temporal = tp;
                         HIPCHK(h, launch(c, 0));
                         HIPCHK(h, hipEventRecord(h->ev0, h->stream));
                         for (int r = 0; r < reps; ++r) HIPCHK(h, launch(c, r));
@@ -1558,8 +1652,9 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
                         }
                     }
         (prec ? h->cfg32 : h->cfg) = bestc;
-        int v[6] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap, bestc.pipeline, bestc.zigzag, bestc.codes};
-        cache_store(key, v, 6);
+        int v[7] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap, bestc.pipeline, bestc.zigzag, bestc.codes,
+                    bestc.temporal};
+        cache_store(key, v, 7);
     }
     // leave the FP32 work vectors as the mixed loop expects them (0 beyond N_int)
     HIPCHK(h, launch_fill_f32(h->stream, h->N, 0.0f, h->ea));

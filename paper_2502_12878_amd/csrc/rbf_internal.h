@@ -35,9 +35,10 @@ struct SweepCfg {
     int pipeline = 0;         // request the next group's streams before the current gathers
     int zigzag = 0;           // odd sweeps of a sequence visit the slices in reverse order
     int codes = 0;            // read 16-bit segment codes instead of 32-bit column ids (Ell::code)
+    int temporal = 0;         // with codes: ordinary instead of non-temporal operator loads
     bool operator<(const SweepCfg &o) const {
-        return std::tie(waves_per_block, unroll, xcd_remap, pipeline, zigzag, codes) <
-               std::tie(o.waves_per_block, o.unroll, o.xcd_remap, o.pipeline, o.zigzag, o.codes);
+        return std::tie(waves_per_block, unroll, xcd_remap, pipeline, zigzag, codes, temporal) <
+               std::tie(o.waves_per_block, o.unroll, o.xcd_remap, o.pipeline, o.zigzag, o.codes, o.temporal);
     }
 };
 
@@ -124,6 +125,8 @@ struct rbf_handle {
 
     rbf::SweepCfg cfg;    // FP64 sweep family
     rbf::SweepCfg cfg32;  // FP32 inner sweeps
+    rbf::SweepCfg cfgT;   // transposed gather of the adjoint
+    bool tunedT = false;
     int weights_panel = 32;
     double last_sweep_sec = 0.0;
     int64_t last_sweeps = 0;

@@ -13,6 +13,15 @@ namespace {
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
 
+// Stream load of the packed operator: non-temporal (NT, kept out of the
+// caches) or an ordinary load (may stay in the memory-side cache between
+// sweeps).
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_op(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblk, int remap) {
     if (!remap) return bid;
     const int64_t per = nblk >> 3, rem = nblk & 7;
@@ -259,7 +268,7 @@ __device__ __forceinline__ int32_t code_col(uint32_t c, int32_t segreg) {
 
 // Compressed rows (Ell::code): 4 codes per 8-byte vector, weights as pairs
 // (layout 1); len is even, codes are padded to a multiple of 4.
-template <typename T, int U>
+template <typename T, int U, bool NT = true>
 struct RowDotC {
     static_assert(U % 4 == 0, "groups of whole code vectors");
     template <class X>
@@ -274,9 +283,9 @@ struct RowDotC {
             u16x4 c[U / 4];
             V ww[U / 2];
 #pragma unroll
-            for (int q = 0; q < U / 4; ++q) c[q] = __builtin_nontemporal_load(cp + ((k >> 2) + q) * kSlice);
+            for (int q = 0; q < U / 4; ++q) c[q] = ld_op<NT>(cp + ((k >> 2) + q) * kSlice);
 #pragma unroll
-            for (int q = 0; q < U / 2; ++q) ww[q] = __builtin_nontemporal_load(wp + ((k >> 1) + q) * kSlice);
+            for (int q = 0; q < U / 2; ++q) ww[q] = ld_op<NT>(wp + ((k >> 1) + q) * kSlice);
             T xx[U];
 #pragma unroll
             for (int q = 0; q < U / 4; ++q) {
@@ -292,8 +301,8 @@ struct RowDotC {
             }
         }
         for (; k < len; k += 2) {
-            const u16x4 c = __builtin_nontemporal_load(cp + (k >> 2) * kSlice);
-            const V ww = __builtin_nontemporal_load(wp + (k >> 1) * kSlice);
+            const u16x4 c = ld_op<NT>(cp + (k >> 2) * kSlice);
+            const V ww = ld_op<NT>(wp + (k >> 1) * kSlice);
             const uint32_t c0 = (k & 2) ? c.z : c.x, c1 = (k & 2) ? c.w : c.y;
             acc = fma(ww.x, x[code_col(c0, segreg)], acc);
             acc = fma(ww.y, x[code_col(c1, segreg)], acc);
@@ -304,7 +313,7 @@ struct RowDotC {
 
 // RowDotC, software-pipelined: the codes and weights of the next group of U
 // entries are requested before the current group's gathers.
-template <typename T, int U>
+template <typename T, int U, bool NT = true>
 struct RowDotCP {
     static_assert(U % 4 == 0, "groups of whole code vectors");
     template <class X>
@@ -319,9 +328,9 @@ struct RowDotCP {
         V wn[U / 2];
         if (groups > 0) {
 #pragma unroll
-            for (int q = 0; q < U / 4; ++q) cn[q] = __builtin_nontemporal_load(cp + q * kSlice);
+            for (int q = 0; q < U / 4; ++q) cn[q] = ld_op<NT>(cp + q * kSlice);
 #pragma unroll
-            for (int q = 0; q < U / 2; ++q) wn[q] = __builtin_nontemporal_load(wp + q * kSlice);
+            for (int q = 0; q < U / 2; ++q) wn[q] = ld_op<NT>(wp + q * kSlice);
         }
         for (int g = 0; g < groups; ++g) {
             u16x4 cc[U / 4];
@@ -332,9 +341,9 @@ struct RowDotCP {
             for (int q = 0; q < U / 2; ++q) wc[q] = wn[q];
             if (g + 1 < groups) {
 #pragma unroll
-                for (int q = 0; q < U / 4; ++q) cn[q] = __builtin_nontemporal_load(cp + ((g + 1) * (U / 4) + q) * kSlice);
+                for (int q = 0; q < U / 4; ++q) cn[q] = ld_op<NT>(cp + ((g + 1) * (U / 4) + q) * kSlice);
 #pragma unroll
-                for (int q = 0; q < U / 2; ++q) wn[q] = __builtin_nontemporal_load(wp + ((g + 1) * (U / 2) + q) * kSlice);
+                for (int q = 0; q < U / 2; ++q) wn[q] = ld_op<NT>(wp + ((g + 1) * (U / 2) + q) * kSlice);
             }
             T xx[U];
 #pragma unroll
@@ -351,8 +360,8 @@ struct RowDotCP {
             }
         }
         for (int k = groups * U; k < len; k += 2) {
-            const u16x4 c = __builtin_nontemporal_load(cp + (k >> 2) * kSlice);
-            const V ww = __builtin_nontemporal_load(wp + (k >> 1) * kSlice);
+            const u16x4 c = ld_op<NT>(cp + (k >> 2) * kSlice);
+            const V ww = ld_op<NT>(wp + (k >> 1) * kSlice);
             const uint32_t c0 = (k & 2) ? c.z : c.x, c1 = (k & 2) ? c.w : c.y;
             acc = fma(ww.x, x[code_col(c0, segreg)], acc);
             acc = fma(ww.y, x[code_col(c1, segreg)], acc);
@@ -372,22 +381,25 @@ struct Codes {
 
 // Row sum of the calling lane's row of `slice`, from codes where the slice
 // has them, else from the 32-bit ids.
-// LAYOUT 3 / 4 are layouts 1 / 2 read through the codes (kernels compiled
-// for them hold both loops; the others hold only their own, which keeps their
+// LAYOUT 3 / 4 are layouts 1 / 2 read through the codes, 5 / 6 the same with
+// ordinary instead of non-temporal stream loads (kernels compiled for them
+// hold both loops; the others hold only their own, which keeps their
 // registers).
 template <typename T, int U, int LAYOUT, class X>
 __device__ __forceinline__ T row_dot(const Codes &cs, const int64_t *__restrict__ slice_ptr,
                                      const int32_t *__restrict__ idx, const T *__restrict__ w, const X &x,
                                      int64_t slice, int lane, int len) {
-    if constexpr (LAYOUT == 3 || LAYOUT == 4) {
+    if constexpr (LAYOUT >= 3) {
+        constexpr bool NT = LAYOUT <= 4;                    // 5 / 6: ordinary stream loads
+        constexpr bool PIPE = LAYOUT == 4 || LAYOUT == 6;
         if (cs.cmode[slice]) {
             const int32_t segreg = cs.segbase[slice * kSegs + (lane & (kSegs - 1))];
-            if constexpr (LAYOUT == 3)
-                return RowDotC<T, U>::run(cs.code + cs.cptr[slice], segreg, w + slice_ptr[slice], x, lane, len);
+            if constexpr (PIPE)
+                return RowDotCP<T, U, NT>::run(cs.code + cs.cptr[slice], segreg, w + slice_ptr[slice], x, lane, len);
             else
-                return RowDotCP<T, U>::run(cs.code + cs.cptr[slice], segreg, w + slice_ptr[slice], x, lane, len);
+                return RowDotC<T, U, NT>::run(cs.code + cs.cptr[slice], segreg, w + slice_ptr[slice], x, lane, len);
         }
-        return RowDot<T, U, LAYOUT - 2>::run(idx, w, x, slice_ptr[slice], lane, len);
+        return RowDot<T, U, PIPE ? 2 : 1>::run(idx, w, x, slice_ptr[slice], lane, len);
     } else {
         return RowDot<T, U, LAYOUT>::run(idx, w, x, slice_ptr[slice], lane, len);
     }

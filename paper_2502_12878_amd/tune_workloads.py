@@ -51,9 +51,18 @@ def _operators():
             p.compute_weights(m)
         return build
 
+    def adjoint(p):
+        grid("cube2M_adjoint")(p)
+        p.autotune()
+        # one short adjoint builds the transposed operator and tunes its gather
+        import torch
+        N = p.sizes["N"]
+        p.adjoint_f(torch.zeros(N, dtype=torch.float64, device=p.device), 2, 1, 1e-6)
+
     ops = [("cube1M m=4 (FP64 + FP32)", grid("cube1M", 4, True)), ("cube1M m=2", grid("cube1M", 2)),
            ("cube1M m=6", grid("cube1M", 6)), ("cube8M (FP64 + FP32)", grid("cube8M", keep_fp32=True)),
-           ("cube4M bands", bands), ("cube2M adjoint", grid("cube2M_adjoint")), ("mixed boundary 100^3", mixed)]
+           ("cube4M bands", bands), ("cube2M adjoint + transposed gather", adjoint),
+           ("mixed boundary 100^3", mixed)]
     ops += [(f"cube1M m=2 n={n}", cube(100, 2, n)) for n in (30, 40, 60, 80, 100, 130, 168)]
     ops += [(f"cube side {s} m={m}", cube(s, m, 2 * ri.num_monomials(3, m))) for s in (68,) for m in (2, 4, 6)]
     return ops

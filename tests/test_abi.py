@@ -99,3 +99,24 @@ def test_iter_struct_layout_matches_header():
 def test_package_import_does_not_need_a_gpu():
     import paper_2502_12878_amd as pkg
     assert hasattr(pkg, "Problem") and hasattr(pkg, "SolveK")
+
+
+def test_shipped_tuning_file_is_valid():
+    """The tuned shapes shipped for MI355X: JSON, one entry per operator key,
+    every value within the candidate sets the autotuner draws from."""
+    import json
+    path = os.path.join(ROOT, "paper_2502_12878_amd", "tuned_gfx950.json")
+    if not os.path.exists(path):
+        pytest.skip("no shipped tuning file")
+    d = json.load(open(path))
+    assert d
+    for key, v in d.items():
+        kind = key.split("|")[0]
+        assert kind in ("sweep", "sweep32", "sweepT", "weights"), key
+        if kind == "weights":
+            assert v[0] in (8, 16, 32)
+            continue
+        assert len(v) in (6, 7), key
+        assert v[0] in (2, 4, 8) and v[1] in (4, 8, 16), key
+        assert all(x in (0, 1) for x in v[2:]), key
+        assert "gfx950" in key
