@@ -99,7 +99,8 @@ rbf_status rbf_build_nodes(rbf_handle *h, int dim, int64_t side, double jitter_f
                            double *xyz_dev, int8_t *type_dev);
 
 /* Give the handle its node set (copied).  Resets stencils and weights.
- * EINVAL: dim not in 1..3, N < 1 or N > 2^31-1, a type other than 0/1/2,
+ * EINVAL: dim not in 1..3, N < 1 or N > 2^29-1 (the sweeps address the
+ * gathered FP64 vector with 32-bit byte offsets), a type other than 0/1/2,
  * NULL pointers. */
 rbf_status rbf_set_nodes(rbf_handle *h, int dim, int64_t N, const double *xyz_dev, const int8_t *type_dev);
 
@@ -264,13 +265,14 @@ rbf_status rbf_set_weights(rbf_handle *h, const double *w_host, int keep_fp32);
 /* Time candidate kernel shapes for the current operator and keep the fastest
  * (sweep: rows per workgroup, unroll depth, XCD-aware block order, software
  * pipelining, zig-zag slice order, 16-bit column codes, non-temporal or
- * ordinary operator loads; weight solver: panel width).  Results are cached in the JSON file named by the
+ * ordinary operator loads, FP32 weights in the code layout; weight solver:
+ * panel width).  Results are cached in the JSON file named by the
  * RBF_AUTOTUNE_CACHE environment variable (none: not cached), keyed by device
  * architecture and problem shape; a shape found there is used without timing
  * (RBF_AUTOTUNE_FORCE=1 times again and replaces it).  RBF_SWEEP_ZIGZAG=0/1
  * and RBF_SWEEP_CODES=0/1 fix those two choices; RBF_SWEEP_SHAPE="waves,
- * unroll,xcd_remap,pipeline,zigzag,codes[,temporal]" fixes the whole sweep
- * shape and turns the sweep timing off.  Synchronises. */
+ * unroll,xcd_remap,pipeline,zigzag,codes[,temporal[,quad]]" fixes the whole
+ * sweep shape and turns the sweep timing off.  Synchronises. */
 rbf_status rbf_autotune(rbf_handle *h);
 
 /* Layout of the packed interior operator and the sweep shapes in use.
@@ -288,6 +290,8 @@ typedef struct {
     int32_t f32_waves, f32_unroll, f32_xcd_remap, f32_pipeline, f32_zigzag, f32_codes;
     double stream_bytes_f64, stream_bytes_f32;
     int32_t f64_temporal, f32_temporal;  /* code-reading sweeps: ordinary (1) or non-temporal (0) loads */
+    int32_t f32_quad;                    /* FP32 weights of coded slices read in the code layout */
+    int32_t reserved;
 } rbf_operator_info;
 
 /* Fill *info for the current operator (EINVAL without one). */

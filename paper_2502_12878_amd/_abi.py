@@ -52,7 +52,8 @@ class rbf_operator_info(C.Structure):
                 ("f32_waves", C.c_int32), ("f32_unroll", C.c_int32), ("f32_xcd_remap", C.c_int32),
                 ("f32_pipeline", C.c_int32), ("f32_zigzag", C.c_int32), ("f32_codes", C.c_int32),
                 ("stream_bytes_f64", C.c_double), ("stream_bytes_f32", C.c_double),
-                ("f64_temporal", C.c_int32), ("f32_temporal", C.c_int32)]
+                ("f64_temporal", C.c_int32), ("f32_temporal", C.c_int32), ("f32_quad", C.c_int32),
+                ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

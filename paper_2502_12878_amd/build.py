@@ -21,6 +21,7 @@ ARCH = os.environ.get("RBF_OFFLOAD_ARCH", "gfx950")
 SOURCES = {
     "k_sweep.hip": [],
     "k_aux.hip": [],
+    "k_sweep32.hip": [],
     "k_nodes.hip": ["-ffp-contract=off"],
     "k_knn.hip": ["-ffp-contract=off"],
     "k_weights.hip": ["-ffp-contract=off"],

@@ -247,7 +247,8 @@ __global__ __launch_bounds__(64) void k_encode_codes(const int64_t *__restrict__
                                                      const int32_t *__restrict__ slice_len,
                                                      const int32_t *__restrict__ idx, int64_t nslices,
                                                      const int64_t *__restrict__ cptr, uint16_t *__restrict__ code,
-                                                     int32_t *__restrict__ segbase, int8_t *__restrict__ cmode) {
+                                                     int32_t *__restrict__ segbase, int8_t *__restrict__ cmode,
+                                                     const double *__restrict__ w, float *__restrict__ w32q) {
     __shared__ uint16_t blk[kMaxSupport * kSlice];
     __shared__ int32_t list[kSegs];
     const int64_t s = blockIdx.x;
@@ -296,14 +297,17 @@ __global__ __launch_bounds__(64) void k_encode_codes(const int64_t *__restrict__
             while (seg + 1 < cnt && list[seg] != b) ++seg;
             c = (uint16_t)((seg << 12) | (col & (kSegSpan - 1)));
         }
-        out[(int64_t)(k >> 2) * (4 * kSlice) + 4 * lane + (k & 3)] = c;
+        const int64_t at = (int64_t)(k >> 2) * (4 * kSlice) + 4 * lane + (k & 3);
+        out[at] = c;
+        // FP32 weights in the same layout (rounded as the paired FP32 copy)
+        if (w32q) w32q[cptr[s] + at] = k < len ? (float)w[ell_pos(1, base, k, lane)] : 0.0f;
     }
 }
 
 hipError_t launch_encode_codes(hipStream_t s, const Ell &e) {
     if (!e.nslices || e.layout != 1 || !e.code) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_encode_codes, dim3((unsigned)e.nslices), dim3(kSlice), 0, s, e.slice_ptr, e.slice_len, e.idx,
-                       e.nslices, e.cptr, e.code, e.segbase, e.cmode);
+                       e.nslices, e.cptr, e.code, e.segbase, e.cmode, e.w, e.w32q);
     return hipGetLastError();
 }
 

@@ -113,6 +113,7 @@ void drop_operator(rbf_handle *h) {
     free_t(h, h->ell.cptr);
     free_t(h, h->ell.segbase);
     free_t(h, h->ell.cmode);
+    free_t(h, h->ell.w32q);
     h->ell = Ell{};
     free_t(h, h->ellT.slice_ptr);
     free_t(h, h->ellT.slice_len);
@@ -378,7 +379,7 @@ rbf_status rbf_set_nodes(rbf_handle *h, int dim, int64_t N, const double *xyz_de
     if (!h) return RBF_EINVAL;
     h->err.clear();
     if (dim < 1 || dim > 3) return fail(h, RBF_EINVAL, "dim must be 1..3");
-    if (N < 1 || N > INT32_MAX) return fail(h, RBF_EINVAL, "N must be in 1..2^31-1");
+    if (N < 1 || N > kMaxNodes) return fail(h, RBF_EINVAL, "N must be in 1..%" PRId64, (int64_t)kMaxNodes);
     if (!xyz_dev || !type_dev) return fail(h, RBF_EINVAL, "null node pointer");
     DeviceGuard g(h->device);
     drop_stencils(h);
@@ -579,6 +580,7 @@ static rbf_status attach_codes(rbf_handle *h, Ell &e, const std::vector<int32_t>
     ALLOC(h, e.cptr, int64_t, e.nslices + 1);
     ALLOC(h, e.segbase, int32_t, (size_t)kSegs * e.nslices);
     ALLOC(h, e.cmode, int8_t, e.nslices);
+    if (e.w32) ALLOC(h, e.w32q, float, e.celems);
     HIPCHK(h, hipMemcpyAsync(e.cptr, cp.data(), sizeof(int64_t) * (e.nslices + 1), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, launch_encode_codes(h->stream, e));
     std::vector<int8_t> cm((size_t)e.nslices);
@@ -640,7 +642,7 @@ static void sweep_key(const rbf_handle *h, int prec, char *key, size_t len) {
                   e.layout, h->N_int, e.elems, e.max_len, e.coded_slices);
 }
 
-// Apply cached shape values v[7] to c.
+// Apply cached shape values v[8] to c.
 static void apply_shape(SweepCfg &c, const int *v, const Ell &e) {
     c.waves_per_block = v[0];
     c.unroll = v[1];
@@ -649,14 +651,14 @@ static void apply_shape(SweepCfg &c, const int *v, const Ell &e) {
     c.zigzag = v[4];
     c.codes = e.cmode ? v[5] : 0;
     c.temporal = c.codes ? v[6] : 0;
+    c.quad = (c.codes && e.w32q) ? v[7] : 0;
 }
 
-// Cached shape of `key` into v[7]; entries written before the temporal-load
-// choice existed hold 6 values (temporal = 0).
+// Cached shape of `key` into v[8]; older entries hold 6 or 7 values (the
+// missing choices 0).
 static bool lookup_shape(const char *key, int *v) {
-    if (cache_lookup(key, v, 7)) return true;
-    v[6] = 0;
-    return cache_lookup(key, v, 6);
+    v[6] = v[7] = 0;
+    return cache_lookup(key, v, 8) || cache_lookup(key, v, 7) || cache_lookup(key, v, 6);
 }
 
 // RBF_SWEEP_ZIGZAG=0/1 fixes the sweep order (forward only / alternating) and
@@ -670,15 +672,16 @@ static int env_flag(const char *name) {
 static int zigzag_override() { return env_flag("RBF_SWEEP_ZIGZAG"); }
 static int codes_override() { return env_flag("RBF_SWEEP_CODES"); }
 
-// RBF_SWEEP_SHAPE="waves,unroll,xcd_remap,pipeline,zigzag,codes[,temporal]"
+// RBF_SWEEP_SHAPE="waves,unroll,xcd_remap,pipeline,zigzag,codes[,temporal[,quad]]"
 // fixes the whole sweep shape (both precisions) and turns the sweep
 // autotuner off.
 static bool shape_override(SweepCfg *c) {
     const char *z = std::getenv("RBF_SWEEP_SHAPE");
     if (!z || !z[0]) return false;
-    int v[7] = {0, 0, 0, 0, 0, 0, 0};
-    const int got = std::sscanf(z, "%d,%d,%d,%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6]);
-    if (got != 6 && got != 7) return false;
+    int v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int got =
+        std::sscanf(z, "%d,%d,%d,%d,%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7]);
+    if (got < 6) return false;
     if ((v[0] != 2 && v[0] != 4 && v[0] != 8) || (v[1] != 4 && v[1] != 8 && v[1] != 16)) return false;
     c->waves_per_block = v[0];
     c->unroll = v[1];
@@ -687,6 +690,7 @@ static bool shape_override(SweepCfg *c) {
     c->zigzag = v[4] != 0;
     c->codes = v[5] != 0;
     c->temporal = c->codes && v[6] != 0;
+    c->quad = c->codes && v[7] != 0;
     return true;
 }
 
@@ -762,7 +766,7 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
     h->have_w32 = keep_fp32 != 0;
     // a tuned shape for this operator, if cached
     char key[160];
-    int v[7];
+    int v[8];
     for (int prec = 0; prec < 2; ++prec) {
         sweep_key(h, prec, key, sizeof key);
         if (lookup_shape(key, v)) apply_shape(prec ? h->cfg32 : h->cfg, v, e);
@@ -774,8 +778,10 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
     SweepCfg forced;
     if (shape_override(&forced)) {
         if (!e.layout) forced.pipeline = 0;
-        if (!e.cmode) forced.codes = 0;
+        if (!e.cmode) forced.codes = forced.temporal = 0;
+        if (!forced.codes || !e.w32q) forced.quad = 0;
         h->cfg = h->cfg32 = forced;
+        h->cfg.quad = 0;
     }
     return RBF_OK;
 }
@@ -1157,7 +1163,8 @@ static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, d
         float *a = h->ea, *b = h->eb;
         const float dt32 = (float)dt;
         for (int i = 0; i < inner && e == hipSuccess; ++i) {
-            e = launch_sweep_f32(s, h->cfg32, h->ell, Ni, h->r32, a, b, dt32, i & 1);
+            e = (h->cfg32.quad ? launch_sweep_f32q : launch_sweep_f32)(s, h->cfg32, h->ell, Ni, h->r32, a, b, dt32,
+                                                                       i & 1);
             std::swap(a, b);
         }
         if (e == hipSuccess) e = launch_add_correction(s, Ni, h->ua, a);
@@ -1383,7 +1390,7 @@ extern "C" rbf_status rbf_iterate(rbf_handle *h, const double *f_dev, double *u_
 
 // Bytes one sweep streams through the packed operator as stored (see the
 // header), for FP64 (wbytes 8, vbytes 8) or FP32 (4, 4) with or without codes.
-static double stream_bytes(const rbf_handle *h, int wbytes, int vbytes, bool codes) {
+static double stream_bytes(const rbf_handle *h, int wbytes, int vbytes, bool codes, bool quad) {
     const Ell &e = h->ell;
     if (!e.nslices) return 0.0;
     std::vector<int32_t> slen((size_t)e.nslices);
@@ -1397,7 +1404,7 @@ static double stream_bytes(const rbf_handle *h, int wbytes, int vbytes, bool cod
     double b = 0.0;
     for (int64_t s = 0; s < e.nslices; ++s) {
         const double len = slen[s], len4 = (slen[s] + 3) & ~3;
-        b += 12.0 + kSlice * len * wbytes;                                  // header, weights
+        b += 12.0 + kSlice * ((quad && cm[s]) ? len4 : len) * wbytes;       // header, weights
         if (codes && cm[s]) b += 1.0 + 4.0 * kSegs + 8.0 + kSlice * len4 * 2.0;  // mode, segments, offset, codes
         else b += kSlice * len * 4.0;                                       // ids
     }
@@ -1432,8 +1439,9 @@ extern "C" rbf_status rbf_get_operator_info(const rbf_handle *h, rbf_operator_in
     info->f32_codes = b.codes && e.cmode ? 1 : 0;
     info->f64_temporal = info->f64_codes && a.temporal;
     info->f32_temporal = info->f32_codes && b.temporal;
-    info->stream_bytes_f64 = stream_bytes(h, 8, 8, info->f64_codes);
-    info->stream_bytes_f32 = h->have_w32 ? stream_bytes(h, 4, 4, info->f32_codes) : 0.0;
+    info->f32_quad = info->f32_codes && b.quad && e.w32q ? 1 : 0;
+    info->stream_bytes_f64 = stream_bytes(h, 8, 8, info->f64_codes, false);
+    info->stream_bytes_f32 = h->have_w32 ? stream_bytes(h, 4, 4, info->f32_codes, info->f32_quad) : 0.0;
     return RBF_OK;
 }
 
@@ -1481,10 +1489,11 @@ static rbf_status tune_transpose(rbf_handle *h) {
     char key[160];
     std::snprintf(key, sizeof key, "sweepT|%s|L%d|%" PRId64 "|%" PRId64 "|%d|c%" PRId64, h->arch, e.layout,
                   h->N_int, e.elems, e.max_len, e.coded_slices);
-    int v[7];
+    int v[8];
     SweepCfg forced;
     if (shape_override(&forced)) {
         if (!e.cmode) forced.codes = forced.temporal = 0;
+        forced.quad = 0;
         h->cfgT = forced;
     } else if (env_flag("RBF_AUTOTUNE_FORCE") != 1 && lookup_shape(key, v)) {
         apply_shape(h->cfgT, v, e);
@@ -1526,9 +1535,9 @@ static rbf_status tune_transpose(rbf_handle *h) {
                         }
                     }
         h->cfgT = bestc;
-        int vv[7] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap, bestc.pipeline, bestc.zigzag, bestc.codes,
-                     bestc.temporal};
-        cache_store(key, vv, 7);
+        int vv[8] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap, bestc.pipeline, bestc.zigzag, bestc.codes,
+                     bestc.temporal, 0};
+        cache_store(key, vv, 8);
     }
     h->tunedT = true;
     return RBF_OK;
@@ -1605,7 +1614,7 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
     for (int prec = 0; prec < nprec; ++prec) {
         char key[160];
         sweep_key(h, prec, key, sizeof key);
-        int cached[7];
+        int cached[8];
         if (!force && lookup_shape(key, cached)) {  // tuned before for this shape
             apply_shape(prec ? h->cfg32 : h->cfg, cached, h->ell);
             continue;
@@ -1614,8 +1623,9 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
         SweepCfg bestc = prec ? h->cfg32 : h->cfg;
         auto launch = [&](const SweepCfg &c, int r) -> hipError_t {
             if (prec)
-                return launch_sweep_f32(h->stream, c, h->ell, Ni, h->r32, (r & 1) ? h->eb : h->ea,
-                                        (r & 1) ? h->ea : h->eb, 0.0f, r & 1);
+                return (c.quad ? launch_sweep_f32q : launch_sweep_f32)(h->stream, c, h->ell, Ni, h->r32,
+                                                                       (r & 1) ? h->eb : h->ea,
+                                                                       (r & 1) ? h->ea : h->eb, 0.0f, r & 1);
             return launch_sweep_f64(h->stream, c, h->ell, Ni, h->fint, (r & 1) ? h->ub : h->ua,
                                     (r & 1) ? h->ua : h->ub, 0.0, nullptr, r & 1);
         };
@@ -1625,9 +1635,11 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
                     for (int pl : {0, 1})
                     for (int zz : {0, 1})
                     for (int cd : {0, 1})
-                    for (int tp : {0, 1}) {
+                    for (int tp : {0, 1})
+                    for (int qd : {0, 1}) {
                         if (pl && h->ell.layout == 0) continue;
                         if (tp && !cd) continue;
+                        if (qd && (!prec || !cd || !h->ell.w32q)) continue;
                         if (zigzag_override() >= 0 && zz != zigzag_override()) continue;
                         if (cd && !h->ell.cmode) continue;
                         if (codes_override() >= 0 && cd != codes_override() && h->ell.cmode) continue;
@@ -1639,6 +1651,7 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
                         c.zigzag = zz;
                         c.codes = cd;
                         c.temporal = tp;
+                        c.quad = qd;
                         HIPCHK(h, launch(c, 0));
                         HIPCHK(h, hipEventRecord(h->ev0, h->stream));
                         for (int r = 0; r < reps; ++r) HIPCHK(h, launch(c, r));
@@ -1652,9 +1665,9 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
                         }
                     }
         (prec ? h->cfg32 : h->cfg) = bestc;
-        int v[7] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap, bestc.pipeline, bestc.zigzag, bestc.codes,
-                    bestc.temporal};
-        cache_store(key, v, 7);
+        int v[8] = {bestc.waves_per_block, bestc.unroll, bestc.xcd_remap, bestc.pipeline, bestc.zigzag, bestc.codes,
+                    bestc.temporal, bestc.quad};
+        cache_store(key, v, 8);
     }
     // leave the FP32 work vectors as the mixed loop expects them (0 beyond N_int)
     HIPCHK(h, launch_fill_f32(h->stream, h->N, 0.0f, h->ea));

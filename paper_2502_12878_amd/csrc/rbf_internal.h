@@ -18,6 +18,8 @@ constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kSlice = 64;       // rows per slice of the packed operator (= one wavefront)
 constexpr int kMaxSupport = 256; // largest support size accepted
 constexpr int kMaxOrder = 6;     // largest augmentation order accepted
+// Largest node count: the sweeps gather FP64 values at 32-bit byte offsets.
+constexpr int64_t kMaxNodes = ((int64_t)1 << 29) - 1;
 
 // Device-side status word: set by kernels that detect a failure, read by the
 // host at the next synchronisation.  code = rbf_status, info = node id.
@@ -36,9 +38,10 @@ struct SweepCfg {
     int zigzag = 0;           // odd sweeps of a sequence visit the slices in reverse order
     int codes = 0;            // read 16-bit segment codes instead of 32-bit column ids (Ell::code)
     int temporal = 0;         // with codes: ordinary instead of non-temporal operator loads
+    int quad = 0;             // FP32 sweeps with codes: weights in the code layout (Ell::w32q)
     bool operator<(const SweepCfg &o) const {
-        return std::tie(waves_per_block, unroll, xcd_remap, pipeline, zigzag, codes, temporal) <
-               std::tie(o.waves_per_block, o.unroll, o.xcd_remap, o.pipeline, o.zigzag, o.codes, o.temporal);
+        return std::tie(waves_per_block, unroll, xcd_remap, pipeline, zigzag, codes, temporal, quad) <
+               std::tie(o.waves_per_block, o.unroll, o.xcd_remap, o.pipeline, o.zigzag, o.codes, o.temporal, o.quad);
     }
 };
 
@@ -68,6 +71,7 @@ struct Ell {
     int64_t *cptr = nullptr;       // [nslices + 1]
     int32_t *segbase = nullptr;    // [16 nslices]
     int8_t *cmode = nullptr;       // [nslices] 1: slice has codes
+    float *w32q = nullptr;         // [celems] FP32 weights of coded slices in the code layout, or null
     int64_t celems = 0;
     int64_t coded_slices = 0;      // slices with cmode 1
 };
@@ -199,6 +203,8 @@ hipError_t launch_sweep_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int6
                             int parity);
 hipError_t launch_sweep_f32(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const float *r,
                             const float *e_old, float *e_new, float dt, int parity);
+hipError_t launch_sweep_f32q(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const float *r,
+                             const float *e_old, float *e_new, float dt, int parity);
 hipError_t launch_apply_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *u,
                             double *Lu, const double *f, unsigned long long *res_slot);
 hipError_t launch_outer_residual(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
