@@ -345,6 +345,7 @@ hipError_t launch_neumann_apply(hipStream_t s, const Ell &e, int64_t N_int, int6
 }
 
 hipError_t launch_add_correction(hipStream_t s, int64_t N_int, double *u, const float *e) {
+    if (N_int <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_add_correction, dim3(grid1d(N_int, 256)), dim3(256), 0, s, N_int, u, e);
     return hipGetLastError();
 }
@@ -368,16 +369,19 @@ hipError_t launch_transpose_scatter(hipStream_t s, const Ell &e, int64_t N_int, 
 }
 
 hipError_t launch_adjoint_update(hipStream_t s, int64_t N_int, double dt, double *lam, double *acc, double *tmp) {
+    if (N_int <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_adjoint_update, dim3(grid1d(N_int, 256)), dim3(256), 0, s, N_int, dt, lam, acc, tmp);
     return hipGetLastError();
 }
 
 hipError_t launch_gather(hipStream_t s, int64_t n, const int32_t *perm, const double *src, double *dst) {
+    if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather, dim3(grid1d(n, 256)), dim3(256), 0, s, n, perm, src, dst);
     return hipGetLastError();
 }
 
 hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *perm, const double *src, double *dst) {
+    if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scatter, dim3(grid1d(n, 256)), dim3(256), 0, s, n, perm, src, dst);
     return hipGetLastError();
 }
@@ -398,6 +402,7 @@ hipError_t launch_fill_u64(hipStream_t s, int64_t n, unsigned long long v, unsig
     return hipGetLastError();
 }
 hipError_t launch_scale_interior(hipStream_t s, int64_t N, int64_t N_int, double a, const double *src, double *dst) {
+    if (N <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scale_interior, dim3(grid1d(N, 256)), dim3(256), 0, s, N, N_int, a, src, dst);
     return hipGetLastError();
 }
