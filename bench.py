@@ -507,8 +507,9 @@ def run_mixed_bc(side=100, m=4, steps=3000, conv_sides=(21, 31, 46), conv_orders
     slopes = {}
     for mm in conv_orders:
         r = [x for x in conv if x["m"] == mm]
-        slopes[str(mm)] = round(float(np.polyfit(np.log([x["h"] for x in r]), np.log([x["err_inf"] for x in r]),
-                                                 1)[0]), 3)
+        if len(r) >= 2:
+            slopes[str(mm)] = round(float(np.polyfit(np.log([x["h"] for x in r]),
+                                                     np.log([x["err_inf"] for x in r]), 1)[0]), 3)
     return {"workload": f"mixed_bc: [0,1/2]^3, {side}^3 jittered grid (seed {seed}), Dirichlet on the outer faces, "
                         f"zero normal derivative on the inner faces, m={m}, n={n}, dt={alpha}*h^2/6",
             "interior_nodes": nint, "neumann_nodes": nneu, "setup_s": round(setup, 3),
