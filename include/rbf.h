@@ -236,8 +236,9 @@ rbf_status rbf_forward_ckpt(rbf_handle *h, const double *f_dev, const double *u0
  * segment in reverse over the `every`-step checkpoint segments; ckpt_dev may
  * be NULL because this gradient does not depend on the states.  Each
  * transposed step is a gather sweep over L_II^T (built once, deterministic;
- * RBF_TRANSPOSE_SCATTER=1 selects the atomic scatter as for
- * rbf_apply_transpose).  EINVAL when the node set has Neumann nodes. */
+ * the first call also encodes it and picks its launch shape, cached like the
+ * shapes of rbf_autotune; RBF_TRANSPOSE_SCATTER=1 selects the atomic scatter
+ * as for rbf_apply_transpose).  EINVAL when the node set has Neumann nodes. */
 rbf_status rbf_adjoint_f(rbf_handle *h, const double *gK_dev, int64_t K, int64_t every,
                          const double *ckpt_dev, double *grad_f_dev, double dt);
 

@@ -134,14 +134,14 @@ __global__ void k_pack_ell(int64_t row0, int64_t nrows, int32_t n_max, int32_t k
 // for Neumann row j (internal row N_int + j), all from the current iterate.
 // The Neumann rows are few (one face layer), so each slice gets a workgroup
 // of kNeuWaves wavefronts: wavefront q sums the q-th part of the slice's
-// entries, issuing all its index and weight loads before its gathers (two
-// memory round trips for up to kNeuBatch entries), and the partial sums
-// are added in a fixed order.  With u_cur / u_next (supports of interior
-// nodes and the row itself only, so no Neumann row reads another's value)
-// the new value goes straight into both iterate buffers.  With g null,
-// nb[N_int + j] = (D u)_j instead (the derivative).
+// entries, loading index and weight pairs as vectors and issuing a batch of
+// them before its gathers, and the partial sums are added in a fixed order.
+// With u_cur / u_next (supports of interior nodes and the row itself only, so
+// no Neumann row reads another's value) the new value goes straight into both
+// iterate buffers.  With g null, nb[N_int + j] = (D u)_j instead (the
+// derivative).
 constexpr int kNeuWaves = 8;
-constexpr int kNeuBatch = 16;
+constexpr int kNeuBatch = 8;  // entry pairs per batch
 
 template <int LAYOUT>
 __global__ __launch_bounds__(kNeuWaves * 64) void k_neumann_eval(
@@ -153,25 +153,43 @@ __global__ __launch_bounds__(kNeuWaves * 64) void k_neumann_eval(
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int len = slice_len[slice];
     const int64_t base = slice_ptr[slice];
-    const int chunk = (len + kNeuWaves - 1) / kNeuWaves;
-    const int k0 = min(len, wave * chunk), k1 = min(len, k0 + chunk);
     double acc = 0.0;
-    for (int kb = k0; kb < k1; kb += kNeuBatch) {
-        int32_t j[kNeuBatch];
-        double ww[kNeuBatch];
+    if (LAYOUT == 1) {
+        // entry pairs as vectors (len is even): wavefront q takes pairs [p0, p1)
+        const int npair = len >> 1;
+        const int chunk = (npair + kNeuWaves - 1) / kNeuWaves;
+        const int p0 = min(npair, wave * chunk), p1 = min(npair, p0 + chunk);
+        const i32x2 *ip = (const i32x2 *)(idx + base) + lane;
+        const f64x2 *wp = (const f64x2 *)(w + base) + lane;
+        for (int pb = p0; pb < p1; pb += kNeuBatch) {
+            i32x2 j[kNeuBatch];
+            f64x2 ww[kNeuBatch];
 #pragma unroll
-        for (int q = 0; q < kNeuBatch; ++q) {
-            const bool on = kb + q < k1;
-            const int64_t pos = ell_pos(LAYOUT, base, on ? kb + q : k0, lane);
-            j[q] = ld_stream(idx + pos);
-            ww[q] = on ? ld_stream(w + pos) : 0.0;
+            for (int q = 0; q < kNeuBatch; ++q) {
+                const int pq = pb + q < p1 ? pb + q : p0;
+                j[q] = ld_stream(ip + (int64_t)pq * kSlice);
+                ww[q] = ld_stream(wp + (int64_t)pq * kSlice);
+            }
+            double xx[2 * kNeuBatch];
+#pragma unroll
+            for (int q = 0; q < kNeuBatch; ++q) {
+                xx[2 * q] = u[j[q].x];
+                xx[2 * q + 1] = u[j[q].y];
+            }
+#pragma unroll
+            for (int q = 0; q < kNeuBatch; ++q)
+                if (pb + q < p1) {
+                    acc = fma(ww[q].x, xx[2 * q], acc);
+                    acc = fma(ww[q].y, xx[2 * q + 1], acc);
+                }
         }
-        double xx[kNeuBatch];
-#pragma unroll
-        for (int q = 0; q < kNeuBatch; ++q) xx[q] = u[j[q]];
-#pragma unroll
-        for (int q = 0; q < kNeuBatch; ++q)
-            if (kb + q < k1) acc = fma(ww[q], xx[q], acc);
+    } else {
+        const int chunk = (len + kNeuWaves - 1) / kNeuWaves;
+        const int k0 = min(len, wave * chunk), k1 = min(len, k0 + chunk);
+        for (int k = k0; k < k1; ++k) {
+            const int64_t pos = ell_pos(0, base, k, lane);
+            acc = fma(ld_stream(w + pos), u[ld_stream(idx + pos)], acc);
+        }
     }
     part[wave][lane] = acc;
     __syncthreads();

@@ -1,19 +1,23 @@
 // Sweep kernels of the explicit RBF-FD iteration (Sec. II-C, the Jacobi step
 // u <- u + dt (L_h u - f) with L_h u at a node a weighted sum over its support,
-// Sec. II).  All of them read the packed operator (sliced ELL, 64 rows per
-// slice, entries of a slice stored entry-major so that one wavefront reads
-// contiguous 256 B index and 512 B weight lines per support entry).
+// Sec. II), the single-operator kernels built from the same row sums, and the
+// adjoint's transposed gather.  All of them read a packed operator (sliced
+// ELL, 64 rows per slice = one wavefront; layouts and row sums in row_dot.h).
 //
-// The sweep is bound by HBM bandwidth: per interior node-update it must move
-// 4n bytes of indices, 8n of weights, and 24 of f, u and u_new.  Index and
-// weight streams are read once per sweep and use non-temporal loads so that
-// the gathered solution vector stays in L2 / Infinity Cache.  Rows of a slice
-// are spatial neighbours and support entries are sorted by column id, so the
-// k-th gathers of a wavefront fall on a few adjacent cache lines.
+// The sweep is bound by HBM bandwidth: per interior node-update it moves the
+// row's column ids (4 B each, or 2 B as segment codes), its weights (8 B) and
+// 24 B of f, u and u_new.  Operator streams are read once per sweep, with
+// non-temporal loads or, in the "temporal" layouts, ordinary loads that let
+// the memory-side Infinity Cache keep the end of one sweep for the start of
+// the next (zig-zag order).  Rows of a slice are spatial neighbours and
+// support entries are sorted by column id, so the k-th gathers of a
+// wavefront fall on a few adjacent cache lines.
 //
 // Workgroups are dispatched round-robin over the 8 XCDs; with xcd_remap each
 // XCD instead owns a contiguous range of slices, so its private L2 holds one
-// contiguous window of the gathered vector instead of eight.
+// contiguous window of the gathered vector instead of eight.  The shape
+// (workgroup size, unroll, layout, order) is chosen per operator by the
+// autotuner; every shape sums each row in the same order.
 #include "row_dot.h"
 
 namespace rbf {
