@@ -101,6 +101,7 @@ def time_to_error(s, target, inner=500, max_steps=2_000_000):
     from paper_2502_12878_amd import RBF_MODE_FP64, RBF_MODE_MIXED
     p, wl = s["p"], s["wl"]
     out = {}
+    finals = {}
     for name, mode in (("fp64", RBF_MODE_FP64), ("fp32_refine", RBF_MODE_MIXED)):
         u = s["u0"].clone()
         torch.cuda.synchronize()
@@ -111,8 +112,12 @@ def time_to_error(s, target, inner=500, max_steps=2_000_000):
         out[name] = {"status": st, "steps": rep["steps"], "wall_s": round(time.perf_counter() - t0, 3),
                      "device_s": round(rep["seconds"], 3), "err_inf": rep["err_inf"],
                      "err_mean_abs": rep["err_mean_abs"], "reached": bool(rep["err_met"])}
+        finals[name] = u
     if out["fp64"]["reached"] and out["fp32_refine"]["reached"]:
         out["speedup_fp32_refine"] = round(out["fp64"]["wall_s"] / out["fp32_refine"]["wall_s"], 3)
+    if out["fp64"]["steps"] == out["fp32_refine"]["steps"]:
+        # the two final iterates after the same number of steps
+        out["max_abs_diff_fp32_refine_vs_fp64"] = (finals["fp32_refine"] - finals["fp64"]).abs().max().item()
     return out
 
 

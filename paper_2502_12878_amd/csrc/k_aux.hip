@@ -212,6 +212,20 @@ __global__ __launch_bounds__(kNeuWaves * 64) void k_neumann_eval(
     }
 }
 
+// near[r] = 1 for an interior row whose support holds a Neumann node, else 0.
+__global__ void k_flag_near(int64_t N, int32_t n_max, const int32_t *__restrict__ sten,
+                            const int16_t *__restrict__ nrow, const int8_t *__restrict__ type,
+                            int8_t *__restrict__ near) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    int8_t f = 0;
+    if (type[r] == 0) {
+        const int n = nrow[r];
+        for (int k = 0; k < n; ++k) f |= type[sten[r * (int64_t)n_max + k]] == 2;
+    }
+    near[r] = f;
+}
+
 // Neumann update, second half: store the new values in both iterate buffers.
 __global__ void k_neumann_store(int64_t N_int, int64_t N_neu, const double *__restrict__ nb, double *__restrict__ ua,
                                 double *__restrict__ ub) {
@@ -320,6 +334,13 @@ __global__ __launch_bounds__(64) void k_encode_codes(const int64_t *__restrict__
         // FP32 weights in the same layout (rounded as the paired FP32 copy)
         if (w32q) w32q[cptr[s] + at] = k < len ? (float)w[ell_pos(1, base, k, lane)] : 0.0f;
     }
+}
+
+hipError_t launch_flag_near(hipStream_t s, int64_t N, int32_t n_max, const int32_t *sten, const int16_t *nrow,
+                            const int8_t *type, int8_t *near) {
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flag_near, dim3(grid1d(N, 256)), dim3(256), 0, s, N, n_max, sten, nrow, type, near);
+    return hipGetLastError();
 }
 
 hipError_t launch_encode_codes(hipStream_t s, const Ell &e) {

@@ -27,13 +27,14 @@ namespace {
 template <int WAVES, int U, int LAYOUT, bool REDUCE>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
-    const double *__restrict__ w, Codes cs, int64_t nslices, int64_t N_int, int64_t ncols, const double *__restrict__ f,
-    const double *__restrict__ u_old, double *__restrict__ u_new, double dt, unsigned long long *res_slot,
-    int order) {
-    const int64_t slice = slice_index<WAVES>(nslices, order);
+    const double *__restrict__ w, Codes cs, int64_t s0, int64_t nslices, int64_t N_int, int64_t ncols,
+    const double *__restrict__ f, const double *__restrict__ u_old, double *__restrict__ u_new, double dt,
+    unsigned long long *res_slot, int order) {
+    const int64_t local = slice_index<WAVES>(nslices, order);
+    const int64_t slice = s0 + local;
     const int lane = threadIdx.x & 63;
     unsigned long long bits = 0;
-    if (slice < nslices) {
+    if (local < nslices) {
         const int len = slice_len[slice];
         const double acc = row_dot<double, U, LAYOUT>(cs, slice_ptr, idx, w, BufGather<double>(u_old, ncols), slice, lane, len);
         const int64_t row = slice * kSlice + lane;
@@ -167,16 +168,16 @@ inline Codes codes_of(const Ell &e) { return Codes{e.code, e.cptr, e.segbase, e.
 template <int WV, int UN, int LY>
 struct SweepF64 {
     static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const double *f, const double *uo, double *un,
-                          double dt, unsigned long long *slot, int remap) {
-        if (!e.nslices) return hipSuccess;
-        const unsigned g = grid1d(e.nslices, WV);
+                          double dt, unsigned long long *slot, int remap, int64_t s0, int64_t ns) {
+        if (ns <= 0) return hipSuccess;
+        const unsigned g = grid1d(ns, WV);
         const Codes cs = codes_of(e);
         if (slot)
             hipLaunchKernelGGL((k_sweep_f64<WV, UN, LY, true>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr,
-                               e.slice_len, e.idx, e.w, cs, e.nslices, N_int, e.ncols, f, uo, un, dt, slot, remap);
+                               e.slice_len, e.idx, e.w, cs, s0, ns, N_int, e.ncols, f, uo, un, dt, slot, remap);
         else
             hipLaunchKernelGGL((k_sweep_f64<WV, UN, LY, false>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr,
-                               e.slice_len, e.idx, e.w, cs, e.nslices, N_int, e.ncols, f, uo, un, dt, slot, remap);
+                               e.slice_len, e.idx, e.w, cs, s0, ns, N_int, e.ncols, f, uo, un, dt, slot, remap);
         return hipGetLastError();
     }
 };
@@ -233,10 +234,14 @@ inline int order_flags(const SweepCfg &c, int parity) { return c.xcd_remap | ((c
 
 hipError_t launch_sweep_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
                             const double *u_old, double *u_new, double dt, unsigned long long *res_slot,
-                            int parity) {
+                            int parity, int64_t s0, int64_t ns) {
+    if (s0 < 0 || s0 > e.nslices) return hipErrorInvalidValue;
+    if (ns < 0 || s0 + ns > e.nslices) ns = e.nslices - s0;
     if (use_codes(c, e))
-        return dispatch_codes<SweepF64>(c, s, e, N_int, f, u_old, u_new, dt, res_slot, order_flags(c, parity));
-    return dispatch_shape<SweepF64>(c, e.layout, s, e, N_int, f, u_old, u_new, dt, res_slot, order_flags(c, parity));
+        return dispatch_codes<SweepF64>(c, s, e, N_int, f, u_old, u_new, dt, res_slot, order_flags(c, parity), s0,
+                                        ns);
+    return dispatch_shape<SweepF64>(c, e.layout, s, e, N_int, f, u_old, u_new, dt, res_slot, order_flags(c, parity),
+                                    s0, ns);
 }
 
 hipError_t launch_sweep_f32(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const float *r,

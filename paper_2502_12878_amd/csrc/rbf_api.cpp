@@ -308,6 +308,9 @@ rbf_status rbf_create(rbf_handle **out, int device, void *hip_stream, const rbf_
     std::snprintf(h->arch, sizeof h->arch, "%s", prop.gcnArchName);
     h->num_cus = prop.multiProcessorCount;
     if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&h->cap2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->evf[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->evf[1], hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
         hipHostMalloc((void **)&h->hslots, 16 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
         delete h;
@@ -332,6 +335,9 @@ rbf_status rbf_destroy(rbf_handle *h) {
         drop_graphs(h);
         while (!h->owned.empty()) dfree(h, h->owned.back().first);
         if (h->cap) hipStreamDestroy(h->cap);
+        if (h->cap2) hipStreamDestroy(h->cap2);
+        for (hipEvent_t ev : h->evf)
+            if (ev) hipEventDestroy(ev);
         if (h->ev0) hipEventDestroy(h->ev0);
         if (h->ev1) hipEventDestroy(h->ev1);
         if (h->hslots) hipHostFree(h->hslots);
@@ -670,6 +676,12 @@ static int env_flag(const char *name) {
     return z[0] == '1' ? 1 : 0;
 }
 static int zigzag_override() { return env_flag("RBF_SWEEP_ZIGZAG"); }
+// RBF_NEUMANN_OVERLAP=1 forks each step of a Neumann problem (the far
+// interior slices swept beside the Neumann update, then the rest).  Off by
+// default: on MI355X the sequential step measured faster (0.139 vs 0.148 ms
+// at 1M interior rows), the second sweep launch costing more than the hidden
+// update.
+static bool overlap_neumann() { return env_flag("RBF_NEUMANN_OVERLAP") == 1; }
 static int codes_override() { return env_flag("RBF_SWEEP_CODES"); }
 
 // RBF_SWEEP_SHAPE="waves,unroll,xcd_remap,pipeline,zigzag,codes[,temporal[,quad]]"
@@ -700,24 +712,43 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
     drop_operator(h);
     const int64_t N = h->N, N_int = h->N_int, N_neu = h->N_neu;
     std::vector<int32_t> perm((size_t)N), iperm((size_t)N);
+    // With Neumann nodes, interior rows whose supports hold no Neumann node
+    // ("far" rows) come first, so a step can sweep them while the Neumann
+    // values are being updated.
+    std::vector<int8_t> near((size_t)N, 0);
+    if (N_neu > 0) {
+        int8_t *d_near = nullptr;
+        ALLOC(h, d_near, int8_t, N);
+        HIPCHK(h, launch_flag_near(h->stream, N, h->n_max, h->sten, h->nrow, h->type, d_near));
+        HIPCHK(h, hipMemcpyAsync(near.data(), d_near, (size_t)N, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        dfree(h, d_near);
+    }
+    int64_t n_far = 0;
     {
-        std::vector<int64_t> cnt(2 * (kMaxSupport + 2), 0);
+        // groups: 0 far interior, 1 near interior, 2 Neumann; each by descending
+        // support size, then canonical id
+        auto group = [&](int64_t i) { return h->type_h[i] == 2 ? 2 : (int)near[i]; };
+        const int G = kMaxSupport + 2;
+        std::vector<int64_t> cnt(3 * G, 0);
         for (int64_t i = 0; i < N; ++i)
-            if (h->type_h[i] != 1) cnt[(h->type_h[i] == 2) * (kMaxSupport + 2) + h->nrow_h[i]]++;
-        std::vector<int64_t> off(2 * (kMaxSupport + 2), 0);
+            if (h->type_h[i] != 1) cnt[group(i) * G + h->nrow_h[i]]++;
+        std::vector<int64_t> off(3 * G, 0);
         int64_t acc = 0;
-        for (int g = 0; g < 2; ++g)
+        for (int g = 0; g < 3; ++g)
             for (int n = kMaxSupport; n >= 1; --n) {
-                off[g * (kMaxSupport + 2) + n] = acc;
-                acc += cnt[g * (kMaxSupport + 2) + n];
+                off[g * G + n] = acc;
+                acc += cnt[g * G + n];
+                if (g == 0) n_far += cnt[g * G + n];
             }
         int64_t bpos = N_int + N_neu;
         for (int64_t i = 0; i < N; ++i) {
             if (h->type_h[i] == 1) perm[bpos++] = (int32_t)i;
-            else perm[off[(h->type_h[i] == 2) * (kMaxSupport + 2) + h->nrow_h[i]]++] = (int32_t)i;
+            else perm[off[group(i) * G + h->nrow_h[i]]++] = (int32_t)i;
         }
         for (int64_t k = 0; k < N; ++k) iperm[perm[k]] = (int32_t)k;
     }
+    h->far_slices = N_neu > 0 ? n_far / kSlice : 0;
     ALLOC(h, h->perm, int32_t, N);
     ALLOC(h, h->iperm, int32_t, N);
     HIPCHK(h, hipMemcpyAsync(h->perm, perm.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, h->stream));
@@ -1146,13 +1177,35 @@ static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, d
     if (kind == kGraphF64 || kind == kGraphF64Quiet) {
         if (kind == kGraphF64) e = launch_fill_u64(s, 1, 0ull, h->dslots);
         double *a = start ? h->ub : h->ua, *b = start ? h->ua : h->ub;
+        // With Neumann nodes updated in place, a step forks: the far interior
+        // slices (whose rows read no Neumann value) are swept on a second
+        // capture stream while the Neumann values are updated, then the
+        // remaining slices are swept.  Same per-row arithmetic as one sweep.
+        const bool fork = h->N_neu > 0 && h->neu_direct && h->far_slices > 0 && overlap_neumann();
         for (int64_t i = 0; i < steps && e == hipSuccess; ++i) {
             const bool report = kind == kGraphF64 && i == steps - 1;
-            // Neumann rows first take their values from the current iterate
-            if (h->N_neu > 0)
-                e = launch_neumann_update(s, h->ellN, Ni, h->N_neu, h->wself, h->fint, a, b, h->nb, h->neu_direct);
-            if (e == hipSuccess)
-                e = launch_sweep_f64(s, h->cfg, h->ell, Ni, h->fint, a, b, dt, report ? h->dslots : nullptr, (int)(i & 1));
+            unsigned long long *slot = report ? h->dslots : nullptr;
+            const int par = (int)(i & 1);
+            if (fork) {
+                // the small Neumann launch is queued first so its workgroups
+                // are placed before the far sweep fills the device
+                e = hipEventRecord(h->evf[0], s);
+                if (e == hipSuccess) e = hipStreamWaitEvent(h->cap2, h->evf[0], 0);
+                if (e == hipSuccess)
+                    e = launch_neumann_update(s, h->ellN, Ni, h->N_neu, h->wself, h->fint, a, b, h->nb, true);
+                if (e == hipSuccess)
+                    e = launch_sweep_f64(h->cap2, h->cfg, h->ell, Ni, h->fint, a, b, dt, slot, par, 0, h->far_slices);
+                if (e == hipSuccess) e = hipEventRecord(h->evf[1], h->cap2);
+                if (e == hipSuccess) e = hipStreamWaitEvent(s, h->evf[1], 0);
+                if (e == hipSuccess)
+                    e = launch_sweep_f64(s, h->cfg, h->ell, Ni, h->fint, a, b, dt, slot, par, h->far_slices, -1);
+            } else {
+                // Neumann rows first take their values from the current iterate
+                if (h->N_neu > 0)
+                    e = launch_neumann_update(s, h->ellN, Ni, h->N_neu, h->wself, h->fint, a, b, h->nb,
+                                              h->neu_direct);
+                if (e == hipSuccess) e = launch_sweep_f64(s, h->cfg, h->ell, Ni, h->fint, a, b, dt, slot, par);
+            }
             std::swap(a, b);
         }
     } else if (kind == kGraphMixed) {

@@ -85,6 +85,8 @@ struct rbf_handle {
     int device = 0;
     hipStream_t stream = nullptr;   // borrowed
     hipStream_t cap = nullptr;      // own stream used only for graph capture
+    hipStream_t cap2 = nullptr;     // second capture stream (branch of a forked step)
+    hipEvent_t evf[2] = {nullptr, nullptr};  // fork / join of a captured step
     rbf_allocator alloc{};
     bool custom_alloc = false;
     std::vector<std::pair<void *, size_t>> owned;  // live allocations
@@ -121,6 +123,7 @@ struct rbf_handle {
     double *wself = nullptr;   // [N_neu] own weight of each Neumann row
     double *nb = nullptr;      // [N_neu] new Neumann values of a step
     bool neu_direct = false;   // Neumann supports hold interior nodes only: update in place
+    int64_t far_slices = 0;    // leading slices whose rows read no Neumann node
 
     // iteration vectors (internal order)
     double *ua = nullptr, *ub = nullptr, *fint = nullptr, *tmp = nullptr, *uref = nullptr;
@@ -193,14 +196,17 @@ hipError_t launch_pack_ell(hipStream_t s, int64_t row0, int64_t nrows, int32_t n
                            const int32_t *iperm, const int32_t *sten, const int16_t *nrow, const double *w_can,
                            const Ell &e, double *wself, int32_t *foreign);
 hipError_t launch_encode_codes(hipStream_t s, const Ell &e);
+hipError_t launch_flag_near(hipStream_t s, int64_t N, int32_t n_max, const int32_t *sten, const int16_t *nrow,
+                            const int8_t *type, int8_t *near);
 hipError_t launch_neumann_update(hipStream_t s, const Ell &e, int64_t N_int, int64_t N_neu, const double *wself,
                                  const double *g, double *u_cur, double *u_next, double *nb, bool direct);
 hipError_t launch_neumann_apply(hipStream_t s, const Ell &e, int64_t N_int, int64_t N_neu, const double *wself,
                                 const double *u, double *out);
 // parity: index of the sweep within its sequence (odd sweeps run reversed when c.zigzag is set)
+// s0, ns: the launch covers slices [s0, s0 + ns) (ns < 0: all slices from s0)
 hipError_t launch_sweep_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
                             const double *u_old, double *u_new, double dt, unsigned long long *res_slot,
-                            int parity);
+                            int parity, int64_t s0 = 0, int64_t ns = -1);
 hipError_t launch_sweep_f32(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const float *r,
                             const float *e_old, float *e_new, float dt, int parity);
 hipError_t launch_sweep_f32q(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const float *r,

@@ -223,3 +223,30 @@ def test_neumann_supports_with_boundary_nodes_use_two_phase_update():
     uo, rep_o, st_o = oracle.Operator(typ, idx, w).iterate(f, dt, u0, 2000, 0.0, 500)
     assert st == st_o == 0
     assert np.abs(u.cpu().numpy() - uo).max() <= 1e-11 * np.abs(uo).max()
+
+
+def test_overlapped_neumann_step_is_bitwise_identical(monkeypatch):
+    """A step sweeps the interior rows that read no Neumann value while the
+    Neumann values are updated, then the rest; the iterates are bitwise those
+    of the sequential step and match the oracle."""
+    import torch
+    dim, side, m = 3, 24, 4
+    xyz, typ, normals = ri.mixed_bc_grid(dim, side, 0.3, 17)
+    n = 2 * ri.num_monomials(dim, m)
+    u_ex, f, u0 = ri.manufactured_mixed(dim, xyz, typ)
+    h = 0.5 / (side - 1)
+    dt = 0.15 * h * h / 6
+    out = []
+    for ov in ("0", "1"):
+        monkeypatch.setenv("RBF_NEUMANN_OVERLAP", ov)
+        p = _gpu_setup(xyz, typ, normals, n, m)
+        u = torch.tensor(u0, device="cuda")
+        st, rep = p.iterate(torch.tensor(f, device="cuda"), u, dt, 777, 0.0, 111)
+        assert st == 0
+        out.append((u.cpu().numpy(), rep["res_final"], rep["res_last"]))
+        p.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+    idx, w = oracle.setup(xyz, typ, n, m=m, normals=normals)
+    uo, _, _ = oracle.Operator(typ, idx, w).iterate(f, dt, u0, 777, 0.0, 111)
+    assert np.abs(out[1][0] - uo).max() <= 1e-11 * np.abs(uo).max()
