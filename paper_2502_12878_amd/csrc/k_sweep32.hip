@@ -140,9 +140,9 @@ hipError_t launch_sweep_f32q(hipStream_t s, const SweepCfg &c, const Ell &e, int
         default: return run_f32q<WV, UN, 6>(s, e, N_int, r, e_old, e_new, dt, order);      \
         }                                                                                  \
     }
-    RBF_CASE(2, 4) RBF_CASE(2, 8) RBF_CASE(2, 16)
-    RBF_CASE(4, 4) RBF_CASE(4, 8) RBF_CASE(4, 16)
-    RBF_CASE(8, 4) RBF_CASE(8, 8) RBF_CASE(8, 16)
+    RBF_CASE(2, 4) RBF_CASE(2, 8) RBF_CASE(2, 16) RBF_CASE(2, 32)
+    RBF_CASE(4, 4) RBF_CASE(4, 8) RBF_CASE(4, 16) RBF_CASE(4, 32)
+    RBF_CASE(8, 4) RBF_CASE(8, 8) RBF_CASE(8, 16) RBF_CASE(8, 32)
 #undef RBF_CASE
     return hipErrorInvalidValue;
 }

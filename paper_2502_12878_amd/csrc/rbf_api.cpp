@@ -694,7 +694,11 @@ static bool shape_override(SweepCfg *c) {
     const int got =
         std::sscanf(z, "%d,%d,%d,%d,%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7]);
     if (got < 6) return false;
-    if ((v[0] != 2 && v[0] != 4 && v[0] != 8) || (v[1] != 4 && v[1] != 8 && v[1] != 16)) return false;
+    // 32-entry groups exist only for the FP32 sweep reading weights in the code
+    // layout; the FP64 sweeps then use 16
+    const bool quad = got >= 8 && v[7] && v[5];
+    if ((v[0] != 2 && v[0] != 4 && v[0] != 8) || (v[1] != 4 && v[1] != 8 && v[1] != 16 && !(v[1] == 32 && quad)))
+        return false;
     c->waves_per_block = v[0];
     c->unroll = v[1];
     c->xcd_remap = v[2] != 0;
@@ -811,8 +815,10 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
         if (!e.layout) forced.pipeline = 0;
         if (!e.cmode) forced.codes = forced.temporal = 0;
         if (!forced.codes || !e.w32q) forced.quad = 0;
+        if (!forced.quad && forced.unroll > 16) forced.unroll = 16;
         h->cfg = h->cfg32 = forced;
         h->cfg.quad = 0;
+        h->cfg.unroll = std::min(h->cfg.unroll, 16);
     }
     return RBF_OK;
 }
@@ -1547,6 +1553,7 @@ static rbf_status tune_transpose(rbf_handle *h) {
     if (shape_override(&forced)) {
         if (!e.cmode) forced.codes = forced.temporal = 0;
         forced.quad = 0;
+        forced.unroll = std::min(forced.unroll, 16);
         h->cfgT = forced;
     } else if (env_flag("RBF_AUTOTUNE_FORCE") != 1 && lookup_shape(key, v)) {
         apply_shape(h->cfgT, v, e);
@@ -1683,7 +1690,7 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
                                     (r & 1) ? h->ua : h->ub, 0.0, nullptr, r & 1);
         };
         for (int wv : {2, 4, 8})
-            for (int un : {4, 8, 16})
+            for (int un : {4, 8, 16, 32})
                 for (int rm : {0, 1})
                     for (int pl : {0, 1})
                     for (int zz : {0, 1})
@@ -1693,6 +1700,7 @@ extern "C" rbf_status rbf_autotune(rbf_handle *h) {
                         if (pl && h->ell.layout == 0) continue;
                         if (tp && !cd) continue;
                         if (qd && (!prec || !cd || !h->ell.w32q)) continue;
+                        if (un == 32 && !qd) continue;  // only the FP32 code-layout sweep has 32-entry groups
                         if (zigzag_override() >= 0 && zz != zigzag_override()) continue;
                         if (cd && !h->ell.cmode) continue;
                         if (codes_override() >= 0 && cd != codes_override() && h->ell.cmode) continue;

@@ -117,6 +117,6 @@ def test_shipped_tuning_file_is_valid():
             assert v[0] in (8, 16, 32)
             continue
         assert len(v) in (6, 7, 8), key
-        assert v[0] in (2, 4, 8) and v[1] in (4, 8, 16), key
+        assert v[0] in (2, 4, 8) and v[1] in (4, 8, 16, 32), key
         assert all(x in (0, 1) for x in v[2:]), key
         assert "gfx950" in key

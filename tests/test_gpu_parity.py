@@ -425,7 +425,8 @@ def test_codes_bitwise_identical_with_fallback_slices(monkeypatch):
 
 
 SHAPES = ["2,4,0,0,0,0", "8,16,1,1,1,0", "4,16,1,0,0,1", "4,8,0,1,1,1", "2,16,1,1,0,1", "8,4,0,0,1,1",
-          "4,16,1,1,1,1,1", "2,8,0,0,0,1,1", "4,16,1,1,1,1,1,1", "2,8,0,0,0,1,0,1", "8,4,1,1,0,1,0,1"]
+          "4,16,1,1,1,1,1", "2,8,0,0,0,1,1", "4,16,1,1,1,1,1,1", "2,8,0,0,0,1,0,1", "8,4,1,1,0,1,0,1",
+          "4,32,0,1,1,1,1,1", "2,32,1,0,0,1,0,1"]
 SHAPE_KEYS = ("waves", "unroll", "xcd_remap", "pipeline", "zigzag", "codes", "temporal")
 
 
@@ -440,11 +441,12 @@ def test_sweep_shapes_bitwise_identical(monkeypatch):
         s = _setup_pair(3, 14, 4, 70, 18, keep_fp32=True)
         info = s["p"].operator_info()
         want = ([int(x) for x in shape.split(",")] + [0, 0])[:8]
-        assert [info[f"f64_{k}"] for k in SHAPE_KEYS] == want[:7]
+        want64 = [want[0], min(want[1], 16)] + want[2:7]  # 32-entry groups: FP32 code-layout sweep only
+        assert [info[f"f64_{k}"] for k in SHAPE_KEYS] == want64
         assert [info[f"f32_{k}"] for k in SHAPE_KEYS] + [info["f32_quad"]] == want
         s["p"].autotune()  # a fixed shape turns the sweep tuner off
         info = s["p"].operator_info()
-        assert [info[f"f64_{k}"] for k in SHAPE_KEYS] == want[:7]
+        assert [info[f"f64_{k}"] for k in SHAPE_KEYS] == want64
         u = s["dev"](s["u0"])
         st, _ = s["p"].iterate(s["dev"](s["f"]), u, s["dt"], 333, 0.0, 111)
         assert st == 0
