@@ -2,13 +2,11 @@
 // [A P; P^T 0][w; lambda] = [L Phi; L p] with phi(r) = r^3 and monomials of
 // degree <= m, L = Laplacian).
 //
-// One persistent launch walks a queue of work items of three kinds:
+// One persistent launch walks a queue of work items of two kinds:
 //   SMALL  4 systems with S = n + M <= 40, one wavefront each, matrix in LDS;
-//   MID    1 system with S <= 112 on the whole workgroup, matrix in LDS;
 //   LARGE  1 system with larger S on the whole workgroup: the matrix lives in
-//          a per-workgroup scratch slab (L2 / Infinity Cache resident) and is
-//          factored by panels of `panel` columns staged in LDS together with
-//          the matching block of pivot rows.
+//          a per-workgroup scratch slab and is factored by panels of 8 or 16
+//          columns staged in LDS.
 // Items are queued largest first so the tail of the launch is short.
 //
 // Every path performs, element by element, the same floating-point
@@ -28,9 +26,8 @@ namespace {
 
 constexpr int kBS = 256;  // threads per workgroup
 constexpr int kSmallS = 40;
-constexpr int kMidS = 112;
 
-enum ItemKind : int32_t { kSmall = 0, kMid = 1, kLarge = 2 };
+enum ItemKind : int32_t { kSmall = 0, kLarge = 1 };
 
 struct Item {
     int32_t kind;
@@ -150,6 +147,21 @@ __device__ __forceinline__ double entry(int k, int l, int n, int M, int S, int d
     return p;
 }
 
+// Maximum over the T threads of a group (T = 64 or a multiple of 64): a
+// wavefront reduction, then the wavefronts' results through red[].  The
+// maximum of a set does not depend on the order it is taken in.
+__device__ double group_max(double v, int t, int T, double *red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if (T == 64) return v;
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    double m = red[0];
+    for (int q = 1; q < T / 64; ++q) m = fmax(m, red[q]);
+    __syncthreads();
+    return m;
+}
+
 // Per-system preamble: scale s and local coordinates y (LDS), run by the
 // threads [t0, t0 + T) of the system's group.  Returns s (read after a
 // workgroup barrier by the caller).
@@ -158,15 +170,8 @@ __device__ void local_coords(const WCtx &cx, int64_t c, int n, double *y, double
     const int32_t *st = cx.sten + c * (int64_t)cx.n_max;
     double mx = 0.0;
     for (int k = t; k < n; k += T) mx = fmax(mx, d2_exact(cx.dim, cx.xyz, cx.N, st[k], c));
-    red[t] = mx;
-    __syncthreads();
-    if (t == 0) {
-        double m2 = 0.0;
-        for (int q = 0; q < T; ++q) m2 = red[q] > m2 ? red[q] : m2;
-        *s_out = sqrt(m2);
-    }
-    __syncthreads();
-    const double s = *s_out;
+    const double s = sqrt(group_max(mx, t, T, red));
+    if (t == 0) *s_out = s;
     for (int q = t; q < 3 * n; q += T) {
         const int k = q / 3, a = q % 3;
         y[q] = a < cx.dim ? (cx.xyz[a * cx.N + st[k]] - cx.xyz[a * cx.N + c]) / s : 0.0;
@@ -254,7 +259,7 @@ __device__ bool gepp_lds(double *A, int S, int ld, double *lv, double *xs, Group
     return !dead;
 }
 
-// SMALL and MID items: T threads per system, 256 / T systems per item.
+// SMALL items: T threads per system, 256 / T systems per item.
 template <int T>
 __device__ void solve_lds_item(const WCtx &cx, const Item &it, char *lds, int S_lds) {
     const int grp = threadIdx.x / T, t = threadIdx.x % T;
@@ -294,11 +299,8 @@ __device__ void solve_lds_item(const WCtx &cx, const Item &it, char *lds, int S_
         A[k * ld + l] = v;
         if (l < S) amax = fmax(amax, fabs(v));
     }
-    red[t] = amax;
-    __syncthreads();
+    const double mm = group_max(amax, t, T, red);
     if (t == 0) {
-        double mm = 0.0;
-        for (int q = 0; q < T; ++q) mm = red[q] > mm ? red[q] : mm;
         gs->tiny = mm * 0x1p-45;
         gs->bad = 0;
     }
@@ -319,10 +321,184 @@ __device__ void solve_lds_item(const WCtx &cx, const Item &it, char *lds, int S_
     __syncthreads();
 }
 
-// LARGE item: whole workgroup, matrix in a global slab, panels in LDS.
+// LARGE item: whole workgroup, matrix in a global slab (row stride
+// blocked_ld(S), a multiple of 4 doubles so a thread's 4-column tile row is
+// two aligned 16-byte loads), factored by panels of PB columns staged in LDS.
+//
+// Per panel:
+//   1. stage the panel (rows k0.., PB columns) in LDS, row stride PB + 1 so a
+//      column read by 64 lanes hits distinct banks;
+//   2. factor it: per step, the pivot is known from the previous step; the
+//      row swap (columns != kk) and the scaling of column kk touch disjoint
+//      entries and share one barrier; the rank-1 update of column kk + 1 and
+//      the search for the next pivot are done by wavefront 0 while the other
+//      wavefronts update the remaining columns (two barriers per step);
+//   3. per trailing column, one pass: gather the rows the panel's swaps touch
+//      (independent loads), finish the pivot rows (U12) in registers, store;
+//   4. trailing update in 4x4 register tiles, the next tile's loads issued
+//      before the current tile is computed.
+// Back substitution runs by blocks of kBB columns: the diagonal block is
+// staged in LDS for wavefront 0, and every row above it loads its kBB
+// entries at once while the block is solved.
+constexpr int kBB = 16;
+
+struct BlockedScratch {
+    int p;       // pivot row of the current step, relative to the panel
+    int bad;
+    int nt;      // rows touched by the panel's swaps
+    int pad;
+    double piv;  // pivot value
+    double okk;  // entry (kk, kk) before the swap
+    double s;
+    double tiny;
+};
+
+template <int PB>
+struct BlockedLds {
+    double *y, *red, *Lp, *Ub, *bx;
+    double *slot, *rowk;       // per step parity: each wavefront's candidate pivot row; row kk
+    unsigned long long *skey;  // per step parity and wavefront: |candidate| as bits
+    int *srow;                 // per step parity and wavefront: candidate row
+    int *pivs, *tsrc, *tdst;
+    int8_t *ex;
+    BlockedScratch *gs;
+    static constexpr int NW = kBS / 64;
+    static constexpr int kSlotDoubles = 2 * NW * PB + 2 * PB + 2 * NW;  // slot, rowk, skey
+    static constexpr int LP = PB + 1;
+    // The panel area holds, in turn, the local coordinates (3n <= 3S
+    // doubles), the panels (S + 4 rows: a 4-row tile past the last row reads
+    // padding) and the diagonal blocks of the back substitution.
+    __host__ __device__ static int lp_doubles(int S) {
+        const int a = (S + 4) * LP, b = kBB * (kBB + 1);
+        return ((a > b ? a : b) + 1) & ~1;
+    }
+    // The U12 rows (PB x ld) also serve as the reduction buffer (kBS doubles).
+    __host__ __device__ static int ub_doubles(int S) {
+        const int a = PB * blocked_ld(S);
+        return a > kBS ? a : kBS;
+    }
+    __host__ __device__ static size_t bytes(int S) {
+        return (size_t)(lp_doubles(S) + ub_doubles(S) + ((S + 1) & ~1) + kSlotDoubles) * sizeof(double) +
+               (3 * 64 + 2 * NW) * sizeof(int) + 84 * 3 + 16 + sizeof(BlockedScratch);
+    }
+    __device__ BlockedLds(char *lds, int S) {
+        Lp = (double *)lds;
+        y = Lp;
+        Ub = Lp + lp_doubles(S);
+        red = Ub;
+        bx = Ub + ub_doubles(S);
+        slot = bx + ((S + 1) & ~1);
+        rowk = slot + 2 * NW * PB;
+        skey = (unsigned long long *)(rowk + 2 * PB);
+        srow = (int *)(skey + 2 * NW);
+        pivs = srow + 2 * NW;
+        tsrc = pivs + 64;
+        tdst = tsrc + 64;
+        ex = (int8_t *)(tdst + 64);
+        gs = (BlockedScratch *)(((uintptr_t)(ex + 84 * 3) + 15) & ~(uintptr_t)15);
+    }
+};
+
+// Wavefront-wide (max |v|, first row) with the signed value of the winner.
+__device__ __forceinline__ void wave_argmax(double &best, int &p, double &val) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int op = __shfl_xor(p, off, 64);
+        const double ov = __shfl_xor(val, off, 64);
+        if (ob > best || (ob == best && op < p)) {
+            best = ob;
+            p = op;
+            val = ov;
+        }
+    }
+}
+
+// Panel factorization with the panel's rows in registers, thread t holding
+// row k0 + t (needs S <= kBS).  Per step, one barrier: each wavefront puts its
+// candidate pivot row (first row of largest |a|) and the current row kk in
+// LDS; after the barrier every thread picks the winner, the threads of rows
+// kk and p exchange contents, and the rows below update.  The operations on
+// each entry are those of the LDS path.  Leaves the panel in Lp and the pivot
+// rows in L.pivs; false if a pivot is not above tiny.
+template <int PB>
+__device__ bool factor_panel_regs(const BlockedLds<PB> &L, const double *A, int ld, int k0, int kb, int prow,
+                                  double tiny, int t, int lane, int wave) {
+    constexpr int LP = PB + 1;
+    constexpr int NW = BlockedLds<PB>::NW;
+    const bool mine = t < prow;
+    double a[PB];
+#pragma unroll
+    for (int j = 0; j < PB; ++j) a[j] = (mine && j < kb) ? A[(int64_t)(k0 + t) * ld + k0 + j] : 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int kk = 0; kk < PB; ++kk) {
+        if (kk >= kb) break;
+        const int buf = kk & 1;
+        const double cv = a[kk];
+        unsigned long long key = 0;
+        if (mine && t >= kk && cv == cv) key = (unsigned long long)__double_as_longlong(fabs(cv));
+        unsigned long long wmax = key;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(wmax, off, 64);
+            wmax = o > wmax ? o : wmax;
+        }
+        const int cl = __ffsll((long long)__ballot(key == wmax)) - 1;
+        if (lane == cl) {
+            L.skey[buf * NW + wave] = wmax;
+            L.srow[buf * NW + wave] = t;
+#pragma unroll
+            for (int j = 0; j < PB; ++j) L.slot[(buf * NW + wave) * PB + j] = a[j];
+        }
+        if (t == kk) {
+#pragma unroll
+            for (int j = 0; j < PB; ++j) L.rowk[buf * PB + j] = a[j];
+        }
+        __syncthreads();
+        int w = 0;
+        unsigned long long bk = L.skey[buf * NW];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) {
+            const unsigned long long kq = L.skey[buf * NW + q];
+            if (kq > bk) { bk = kq; w = q; }
+        }
+        if (!(__longlong_as_double((long long)bk) > tiny)) { ok = false; break; }
+        const int p = L.srow[buf * NW + w];
+        if (t == 0) L.pivs[kk] = k0 + p;
+        const double *u = L.slot + (buf * NW + w) * PB;
+        if (t == kk) {
+#pragma unroll
+            for (int j = 0; j < PB; ++j) a[j] = u[j];
+        } else if (t == p) {
+#pragma unroll
+            for (int j = 0; j < PB; ++j) a[j] = L.rowk[buf * PB + j];
+        }
+        if (mine && t > kk) {
+            const double l = a[kk] / u[kk];
+            a[kk] = l;
+#pragma unroll
+            for (int j = kk + 1; j < PB; ++j)
+                if (j < kb) {
+                    const double prod = l * u[j];
+                    a[j] = a[j] - prod;
+                }
+        }
+    }
+    if (mine) {
+#pragma unroll
+        for (int j = 0; j < PB; ++j) L.Lp[t * LP + j] = a[j];
+    }
+    __syncthreads();
+    return ok;
+}
+
+template <int PB>
 __device__ void solve_blocked_item(const WCtx &cx, const Item &it, char *lds) {
+    constexpr int LP = PB + 1;
     const int t = threadIdx.x;
     const int lane = t & 63;
+    const int wave = t >> 6;
     const int64_t li = it.first;
     const int64_t c = cx.rows[li];
     const int n = cx.nrow[c];
@@ -330,160 +506,272 @@ __device__ void solve_blocked_item(const WCtx &cx, const Item &it, char *lds) {
     const int M = num_monomials(cx.dim, m);
     const int S = n + M;
     const int C = S + 1;
-    const int ld = C;
-    const int PB = cx.panel;
+    const int ld = blocked_ld(S);
     double *A = cx.scratch + (int64_t)blockIdx.x * cx.slab;
-
-    // LDS: y | red | Lp [S][PB] | Ub [PB][C] | lv | piv idx | ex | scalars
-    double *y = (double *)lds;
-    double *red = y + 3 * kMaxSupport;
-    double *Lp = red + kBS;
-    double *Ub = Lp + (size_t)S * PB;
-    double *bx = Ub + (size_t)PB * C;          // rhs / solution vector [S]
-    int *pivs = (int *)(bx + S);
-    int8_t *ex = (int8_t *)(pivs + 64);
-    GroupScratch *gs = (GroupScratch *)(((uintptr_t)(ex + 84 * 3) + 15) & ~(uintptr_t)15);
+    BlockedLds<PB> L(lds, S);
+    BlockedScratch *gs = L.gs;
+    double *Lp = L.Lp, *Ub = L.Ub, *bx = L.bx;
 
     const int op = cx.type[c] == 2 ? 1 : 0;
     double nv[3] = {0.0, 0.0, 0.0};
     if (op)
         for (int a = 0; a < cx.dim; ++a) nv[a] = cx.normals[a * cx.N + c];
-    if (t == 0) make_exponents(cx.dim, m, ex);
-    local_coords(cx, c, n, y, &gs->s, t, kBS, red);
+    if (t == 0) make_exponents(cx.dim, m, L.ex);
+    local_coords(cx, c, n, L.y, &gs->s, t, kBS, L.red);
     __syncthreads();
     const double s = gs->s;
     double amax = 0.0;
-    for (int64_t q = t; q < (int64_t)S * C; q += kBS) {
-        const int k = (int)(q / C), l = (int)(q % C);
-        const double v = entry(k, l, n, M, S, cx.dim, y, ex, op, nv);
-        A[(int64_t)k * ld + l] = v;
-        if (l < S) amax = fmax(amax, fabs(v));
+    // Rows by wavefront, columns by lane.  Entry (k, l) of the r^3 block
+    // equals entry (l, k) bit for bit (y_k - y_l is exactly -(y_l - y_k)) and
+    // entry (n + j, k) of P^T equals entry (k, n + j) of P: each is computed
+    // once and stored at both places.
+    for (int r = wave; r < S; r += kBS / 64) {
+        double *Ar = A + (int64_t)r * ld;
+        if (r < n) {
+            for (int l = r + lane; l < n; l += 64) {
+                const double v = entry(r, l, n, M, S, cx.dim, L.y, L.ex, op, nv);
+                Ar[l] = v;
+                A[(int64_t)l * ld + r] = v;
+                amax = fmax(amax, fabs(v));
+            }
+        } else {
+            for (int l = lane; l < n; l += 64) {
+                const double v = entry(r, l, n, M, S, cx.dim, L.y, L.ex, op, nv);
+                Ar[l] = v;
+                A[(int64_t)l * ld + r] = v;
+                amax = fmax(amax, fabs(v));
+            }
+            for (int l = n + lane; l < S; l += 64) Ar[l] = 0.0;
+        }
+        if (lane == 0) Ar[S] = entry(r, S, n, M, S, cx.dim, L.y, L.ex, op, nv);
     }
-    red[t] = amax;
-    __syncthreads();
+    const double mm = group_max(amax, t, kBS, L.red);
     if (t == 0) {
-        double mm = 0.0;
-        for (int q = 0; q < kBS; ++q) mm = red[q] > mm ? red[q] : mm;
         gs->tiny = mm * 0x1p-45;
         gs->bad = !(s > 0.0);
     }
     __syncthreads();
     bool ok = !gs->bad;
+    const double tiny = gs->tiny;
 
     for (int k0 = 0; ok && k0 < S; k0 += PB) {
         const int kb = min(PB, S - k0);
         const int prow = S - k0;
-        // stage the panel: rows k0.., columns k0..k0+kb-1
-        for (int q = t; q < prow * kb; q += kBS) {
-            const int i = q / kb, j = q % kb;
-            Lp[i * PB + j] = A[(int64_t)(k0 + i) * ld + k0 + j];
-        }
-        __syncthreads();
-        // factor the panel; multipliers overwrite the eliminated entries
-        for (int kk = 0; kk < kb; ++kk) {
-            const int k = k0 + kk;
-            if (t < 64) {
-                double best = -1.0;
-                int p = S;
-                for (int i = kk + lane; i < prow; i += 64) {
-                    const double v = fabs(Lp[i * PB + kk]);
-                    if (v > best) { best = v; p = i; }
+        if (S <= kBS) {
+            ok = factor_panel_regs<PB>(L, A, ld, k0, kb, prow, tiny, t, lane, wave);
+        } else {
+        {  // stage the panel: 8 loads in flight per thread before the LDS stores
+            constexpr int RS = kBS / PB;  // rows per pass
+            const int j = t % PB, i0 = t / PB;
+            for (int base = 0; base < prow; base += 8 * RS) {
+                double v[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int i = base + i0 + RS * r;
+                    v[r] = (i < prow && j < kb) ? A[(int64_t)(k0 + i) * ld + k0 + j] : 0.0;
                 }
 #pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    const double ob = __shfl_xor(best, off, 64);
-                    const int op = __shfl_xor(p, off, 64);
-                    if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
-                }
-                if (lane == 0) {
-                    gs->p = p;
-                    gs->bad = !(best > gs->tiny);
-                    pivs[kk] = k0 + p;
+                for (int r = 0; r < 8; ++r) {
+                    const int i = base + i0 + RS * r;
+                    if (i < prow && j < kb) Lp[i * LP + j] = v[r];
                 }
             }
-            __syncthreads();
+        }
+        __syncthreads();
+        if (wave == 0) {  // pivot of the panel's first column
+            double best = -1.0, val = 0.0;
+            int p = S;
+            for (int i = lane; i < prow; i += 64) {
+                const double v = Lp[i * LP];
+                if (fabs(v) > best) { best = fabs(v); p = i; val = v; }
+            }
+            wave_argmax(best, p, val);
+            if (lane == 0) {
+                gs->p = p;
+                gs->bad = !(best > tiny);
+                gs->piv = val;
+                gs->okk = Lp[0];
+                L.pivs[0] = k0 + p;
+            }
+        }
+        __syncthreads();
+        for (int kk = 0; kk < kb; ++kk) {
             if (gs->bad) { ok = false; break; }
             const int p = gs->p;
-            if (p != kk)
-                for (int j = t; j < kb; j += kBS) {
-                    const double a = Lp[kk * PB + j];
-                    Lp[kk * PB + j] = Lp[p * PB + j];
-                    Lp[p * PB + j] = a;
-                }
-            __syncthreads();
-            const double piv = Lp[kk * PB + kk];
-            for (int i = kk + 1 + t; i < prow; i += kBS) Lp[i * PB + kk] = Lp[i * PB + kk] / piv;
-            __syncthreads();
-            const int cols = kb - kk - 1, rows = prow - kk - 1;
-            for (int q = t; q < rows * cols; q += kBS) {
-                const int i = kk + 1 + q / cols, j = kk + 1 + q % cols;
-                const double prod = Lp[i * PB + kk] * Lp[kk * PB + j];
-                Lp[i * PB + j] = Lp[i * PB + j] - prod;
+            const double piv = gs->piv;
+            const double okk = gs->okk;
+            // swap rows kk and p on the columns other than kk ...
+            if (p != kk && t < kb && t != kk) {
+                const double a = Lp[kk * LP + t];
+                Lp[kk * LP + t] = Lp[p * LP + t];
+                Lp[p * LP + t] = a;
+            }
+            // ... and the multipliers of column kk, from the rows before the swap
+            for (int i = kk + t; i < prow; i += kBS) {
+                if (i == kk) Lp[kk * LP + kk] = piv;
+                else Lp[i * LP + kk] = ((i == p) ? okk : Lp[i * LP + kk]) / piv;
             }
             __syncthreads();
-            (void)k;
+            if (wave == 0) {
+                if (kk + 1 < kb) {  // column kk + 1, then its pivot
+                    const int j = kk + 1;
+                    const double ukj = Lp[kk * LP + j];
+                    double best = -1.0, val = 0.0, first = 0.0;
+                    int pb = S;
+                    for (int i = kk + 1 + lane; i < prow; i += 64) {
+                        const double prod = Lp[i * LP + kk] * ukj;
+                        const double v = Lp[i * LP + j] - prod;
+                        Lp[i * LP + j] = v;
+                        if (i == kk + 1) first = v;
+                        if (fabs(v) > best) { best = fabs(v); pb = i; val = v; }
+                    }
+                    wave_argmax(best, pb, val);
+                    if (lane == 0) {
+                        gs->p = pb;
+                        gs->bad = !(best > tiny);
+                        gs->piv = val;
+                        gs->okk = first;
+                        L.pivs[j] = k0 + pb;
+                    }
+                }
+            } else if (kk + 2 < kb) {  // columns kk + 2 .. kb - 1
+                constexpr int RS = (kBS - 64) / PB;  // row slots
+                const int u = t - 64;
+                const int j = kk + 2 + u % PB;
+                if (j < kb) {
+                    const double ukj = Lp[kk * LP + j];
+                    for (int i = kk + 1 + u / PB; i < prow; i += RS) {
+                        const double prod = Lp[i * LP + kk] * ukj;
+                        Lp[i * LP + j] = Lp[i * LP + j] - prod;
+                    }
+                }
+            }
+            __syncthreads();
+        }
         }
         if (!ok) break;
-        // write back the panel's pivot rows (upper part incl. diagonal)
-        for (int q = t; q < kb * kb; q += kBS) {
-            const int i = q / kb, j = q % kb;
-            if (j >= i) A[(int64_t)(k0 + i) * ld + k0 + j] = Lp[i * PB + j];
+        // the panel's pivot rows (upper part incl. the diagonal) back to the slab
+        for (int q = t; q < kb * PB; q += kBS) {
+            const int i = q / PB, j = q % PB;
+            if (j < kb && j >= i) A[(int64_t)(k0 + i) * ld + k0 + j] = Lp[i * LP + j];
         }
-        // deferred row swaps on the trailing columns, in pivot order
+        // where the panel's swaps leave each touched row: position tdst[q]
+        // receives the row that sat at tsrc[q]; the pivot positions k0.. come
+        // first.  Wavefront 0 replays the swaps with lane q holding entry q.
+        if (wave == 0) {
+            int dst = lane < kb ? k0 + lane : -1;
+            int src = dst;
+            int nt = kb;
+            const int mypiv = lane < kb ? L.pivs[lane] : 0;
+            for (int kk = 0; kk < kb; ++kk) {
+                const int pr = __shfl(mypiv, kk, 64);
+                const unsigned long long hit = __ballot(dst == pr);
+                int b;
+                if (hit) {
+                    b = __ffsll((long long)hit) - 1;
+                } else {
+                    b = nt;
+                    if (lane == nt) { dst = pr; src = pr; }
+                    ++nt;
+                }
+                const int sa = __shfl(src, kk, 64), sb = __shfl(src, b, 64);
+                if (lane == kk) src = sb;
+                if (lane == b) src = sa;
+            }
+            if (lane < nt) { L.tdst[lane] = dst; L.tsrc[lane] = src; }
+            if (lane == 0) gs->nt = nt;
+        }
+        __syncthreads();
         const int j0 = k0 + kb;
         const int tc = C - j0;
-        for (int j = j0 + t; j < C; j += kBS)
-            for (int kk = 0; kk < kb; ++kk) {
-                const int p = pivs[kk];
-                if (p != k0 + kk) {
-                    const double a = A[(int64_t)(k0 + kk) * ld + j];
-                    A[(int64_t)(k0 + kk) * ld + j] = A[(int64_t)p * ld + j];
-                    A[(int64_t)p * ld + j] = a;
+        const int nt = gs->nt;
+        // swaps and U12 of each trailing column in one pass
+        for (int cc = t; cc < tc; cc += kBS) {
+            const int j = j0 + cc;
+            double v[2 * PB];
+#pragma unroll
+            for (int q = 0; q < 2 * PB; ++q)
+                if (q < nt) v[q] = A[(int64_t)L.tsrc[q] * ld + j];
+#pragma unroll
+            for (int kk = 1; kk < PB; ++kk) {
+                if (kk < kb) {
+                    double u = v[kk];
+#pragma unroll
+                    for (int q = 0; q < kk; ++q) {
+                        const double prod = Lp[kk * LP + q] * v[q];
+                        u = u - prod;
+                    }
+                    v[kk] = u;
                 }
             }
+#pragma unroll
+            for (int q = 0; q < 2 * PB; ++q)
+                if (q < nt) A[(int64_t)L.tdst[q] * ld + j] = v[q];
+#pragma unroll
+            for (int kk = 0; kk < PB; ++kk)
+                if (kk < kb) Ub[kk * ld + cc] = v[kk];
+        }
         __syncthreads();
-        // U12: the panel's pivot rows over the trailing columns
-        for (int j = j0 + t; j < C; j += kBS)
-            for (int kk = 0; kk < kb; ++kk) {
-                double v = A[(int64_t)(k0 + kk) * ld + j];
-                for (int q = 0; q < kk; ++q) {
-                    const double prod = Lp[kk * PB + q] * Ub[q * C + (j - j0)];
-                    v = v - prod;
-                }
-                Ub[kk * C + (j - j0)] = v;
-                A[(int64_t)(k0 + kk) * ld + j] = v;
-            }
-        __syncthreads();
-        // trailing update with 4x4 register tiles
+        // trailing update, 4x4 tiles; a tile row is 4 aligned columns (the
+        // padding columns up to ld are read, never stored)
         const int tr = S - j0;
-        const int ti = (tr + 3) / 4, tj = (tc + 3) / 4;
-        for (int q = t; q < ti * tj; q += kBS) {
+        const int ti = (tr + 3) >> 2, tj = (tc + 3) >> 2;
+        const int ntiles = ti * tj;
+        double cur[4][4], nxt[4][4];
+        auto load_tile = [&](int q, double (&dst)[4][4]) {
             const int i0 = j0 + (q / tj) * 4, c0 = (q % tj) * 4;
-            double acc[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                if (i0 + a < S) {
+                    const double2 *src = (const double2 *)(A + (int64_t)(i0 + a) * ld + j0 + c0);
+                    const double2 lo = src[0], hi = src[1];
+                    dst[a][0] = lo.x; dst[a][1] = lo.y; dst[a][2] = hi.x; dst[a][3] = hi.y;
+                } else {
+                    dst[a][0] = dst[a][1] = dst[a][2] = dst[a][3] = 0.0;
+                }
+            }
+        };
+        // with 16-column panels (two workgroups per CU) the next tile's loads
+        // are issued before the current tile is computed; with 8-column
+        // panels more resident workgroups hide the latency instead
+        constexpr bool kPrefetch = PB >= 16;
+        if (kPrefetch && t < ntiles) load_tile(t, cur);
+        for (int q = t; q < ntiles; q += kBS) {
+            if (kPrefetch) {
+                if (q + kBS < ntiles) load_tile(q + kBS, nxt);
+            } else {
+                load_tile(q, cur);
+            }
+            const int i0 = j0 + (q / tj) * 4, c0 = (q % tj) * 4;
+#pragma unroll
+            for (int kk = 0; kk < PB; ++kk) {
+                if (kk < kb) {
+                    double l[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) l[a] = Lp[(i0 + a - k0) * LP + kk];
+                    const double2 u01 = *(const double2 *)(Ub + kk * ld + c0);
+                    const double2 u23 = *(const double2 *)(Ub + kk * ld + c0 + 2);
+                    const double u[4] = {u01.x, u01.y, u23.x, u23.y};
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int b2 = 0; b2 < 4; ++b2) {
+                            const double prod = l[a] * u[b2];
+                            cur[a][b2] = cur[a][b2] - prod;
+                        }
+                }
+            }
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    acc[a][b] = (i0 + a < S && c0 + b < tc) ? A[(int64_t)(i0 + a) * ld + j0 + c0 + b] : 0.0;
-            for (int kk = 0; kk < kb; ++kk) {
-                double l[4], u[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) l[a] = (i0 + a < S) ? Lp[(i0 + a - k0) * PB + kk] : 0.0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) u[b] = (c0 + b < tc) ? Ub[kk * C + c0 + b] : 0.0;
+                for (int b2 = 0; b2 < 4; ++b2)
+                    if (i0 + a < S && c0 + b2 < tc) A[(int64_t)(i0 + a) * ld + j0 + c0 + b2] = cur[a][b2];
+            if (kPrefetch) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const double prod = l[a] * u[b];
-                        acc[a][b] = acc[a][b] - prod;
-                    }
+                    for (int b2 = 0; b2 < 4; ++b2) cur[a][b2] = nxt[a][b2];
             }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (i0 + a < S && c0 + b < tc) A[(int64_t)(i0 + a) * ld + j0 + c0 + b] = acc[a][b];
         }
         __syncthreads();
     }
@@ -495,29 +783,47 @@ __device__ void solve_blocked_item(const WCtx &cx, const Item &it, char *lds) {
         __syncthreads();
         return;
     }
-    // back substitution by columns, 64 columns at a time: wavefront 0 solves
-    // the block's unknowns with shuffles, then every thread applies them to
-    // the rows above in descending column order.
+    // back substitution by columns, kBB at a time from the last unknown
     for (int i = t; i < S; i += kBS) bx[i] = A[(int64_t)i * ld + S];
-    __syncthreads();
-    for (int j1 = S; j1 > 0; j1 -= 64) {
-        const int jb0 = j1 > 64 ? j1 - 64 : 0;
-        if (t < 64) {
-            const int i = jb0 + lane;
-            double b = i < j1 ? bx[i] : 0.0;
-            for (int j = j1 - 1; j >= jb0; --j) {
-                const double bj = __shfl(b, j - jb0, 64);
-                const double xj = bj / A[(int64_t)j * ld + j];
-                if (i == j) b = xj;
-                if (i < j) {
-                    const double prod = A[(int64_t)i * ld + j] * xj;
+    double *D = Lp;  // the panel area holds the diagonal block
+    constexpr int DL = kBB + 1;
+    for (int j1 = S; j1 > 0; j1 -= kBB) {
+        const int jb0 = j1 > kBB ? j1 - kBB : 0;
+        const int bs = j1 - jb0;
+        for (int q = t; q < kBB * kBB; q += kBS) {
+            const int r = q / kBB, cc = q % kBB;
+            if (r < bs && cc < bs) D[r * DL + cc] = A[(int64_t)(jb0 + r) * ld + jb0 + cc];
+        }
+        const bool above = t < jb0;
+        double seg[kBB];
+#pragma unroll
+        for (int jj = 0; jj < kBB; ++jj) seg[jj] = (above && jj < bs) ? A[(int64_t)t * ld + jb0 + jj] : 0.0;
+        __syncthreads();
+        if (wave == 0) {
+            double b = lane < bs ? bx[jb0 + lane] : 0.0;
+            for (int j = bs - 1; j >= 0; --j) {
+                const double bj = __shfl(b, j, 64);
+                const double xj = bj / D[j * DL + j];
+                if (lane == j) b = xj;
+                if (lane < j) {
+                    const double prod = D[lane * DL + j] * xj;
                     b = b - prod;
                 }
             }
-            if (i < j1) bx[i] = b;
+            if (lane < bs) bx[jb0 + lane] = b;
         }
         __syncthreads();
-        for (int i = t; i < jb0; i += kBS) {
+        if (above) {
+            double b = bx[t];
+#pragma unroll
+            for (int jj = kBB - 1; jj >= 0; --jj)
+                if (jj < bs) {
+                    const double prod = seg[jj] * bx[jb0 + jj];
+                    b = b - prod;
+                }
+            bx[t] = b;
+        }
+        for (int i = t + kBS; i < jb0; i += kBS) {  // rows beyond one per thread (S > kBS)
             double b = bx[i];
             for (int j = j1 - 1; j >= jb0; --j) {
                 const double prod = A[(int64_t)i * ld + j] * bx[j];
@@ -532,8 +838,14 @@ __device__ void solve_blocked_item(const WCtx &cx, const Item &it, char *lds) {
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kBS) void k_weights(WCtx cx, const Item *__restrict__ items, int64_t nitems,
-                                                 int32_t *counter, int S_small, int S_mid) {
+// One kernel per panel width (PB = 0: no LARGE items), so that each has its
+// own register budget.
+template <int PB>
+constexpr int kWavesPerEu = PB == 8 ? 3 : 2;  // resident workgroups per CU the LDS allows at S = 252
+
+template <int PB>
+__global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<PB>))) void k_weights(WCtx cx, const Item *__restrict__ items, int64_t nitems,
+                                                 int32_t *counter, int S_small) {
     extern __shared__ __align__(16) char lds[];
     __shared__ int64_t s_item;
     for (;;) {
@@ -544,9 +856,14 @@ __global__ __launch_bounds__(kBS) void k_weights(WCtx cx, const Item *__restrict
         if (q >= nitems) return;
         const Item it = items[q];
         if (it.kind == kSmall) solve_lds_item<64>(cx, it, lds, S_small);
-        else if (it.kind == kMid) solve_lds_item<kBS>(cx, it, lds, S_mid);
-        else solve_blocked_item(cx, it, lds);
+        else if constexpr (PB > 0) solve_blocked_item<PB>(cx, it, lds);
     }
+}
+
+const void *weights_kernel(int panel) {
+    if (panel == 8) return (const void *)k_weights<8>;
+    if (panel == 16) return (const void *)k_weights<16>;
+    return (const void *)k_weights<0>;
 }
 
 size_t lds_small_bytes(int S_lds, int T) {
@@ -556,31 +873,28 @@ size_t lds_small_bytes(int S_lds, int T) {
 }
 
 size_t lds_blocked_bytes(int S, int PB) {
-    return (size_t)(3 * kMaxSupport + kBS) * sizeof(double) + (size_t)S * PB * sizeof(double) +
-           (size_t)PB * (S + 1) * sizeof(double) + (size_t)S * sizeof(double) + 64 * sizeof(int) + 84 * 3 + 64;
+    return PB == 8 ? BlockedLds<8>::bytes(S) : BlockedLds<16>::bytes(S);
 }
 
 }  // namespace
 
 int weights_small_limit() { return kSmallS; }
-int weights_mid_limit() { return kMidS; }
+int64_t weights_slab(int S_large) { return S_large > 0 ? (int64_t)S_large * blocked_ld(S_large) + 32 : 0; }
 
-size_t lds_total(int S_small, int S_mid, int S_large, int panel) {
+size_t lds_total(int S_small, int S_large, int panel) {
     size_t lds = 0;
     if (S_small > 0) lds = std::max(lds, lds_small_bytes(S_small, 64));
-    if (S_mid > 0) lds = std::max(lds, lds_small_bytes(S_mid, kBS));
     if (S_large > 0) lds = std::max(lds, lds_blocked_bytes(S_large, panel));
     return (lds + 255) & ~(size_t)255;
 }
 
 // Resident workgroups of the persistent launch on this device (0: does not fit).
-int weights_grid(int S_small, int S_mid, int S_large, int panel) {
-    const size_t lds = lds_total(S_small, S_mid, S_large, panel);
-    if (hipFuncSetAttribute((const void *)k_weights, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-        hipSuccess)
-        return 0;
+int weights_grid(int S_small, int S_large, int panel) {
+    const size_t lds = lds_total(S_small, S_large, panel);
+    const void *kern = weights_kernel(S_large > 0 ? panel : 0);
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_weights, kBS, lds) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBS, lds) != hipSuccess) return 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     return per_cu * cus;
@@ -592,18 +906,27 @@ hipError_t launch_weights_items(hipStream_t s, int dim, int64_t N, const double 
                                 const int16_t *nrow, int32_t n_max, const int32_t *rows, const int8_t *mrow,
                                 const int8_t *type, const double *normals, double *w_out, double *scratch,
                                 int64_t slab, int panel, DevStatus *status, const void *items, int64_t nitems,
-                                int32_t *counter, int S_small, int S_mid, int S_large, int grid, int nslabs,
+                                int32_t *counter, int S_small, int S_large, int grid, int nslabs,
                                 size_t *lds_used) {
     WCtx cx{dim, N, xyz, sten, nrow, n_max, rows, mrow, w_out, type, normals, scratch, slab, panel, status};
-    const size_t lds = lds_total(S_small, S_mid, S_large, panel);
+    const size_t lds = lds_total(S_small, S_large, panel);
     if (lds_used) *lds_used = lds;
     if (grid <= 0) return hipErrorInvalidConfiguration;
     // a LARGE item uses scratch slab blockIdx.x: never launch more groups than slabs
     if (S_large > 0 && (scratch == nullptr || grid > nslabs)) return hipErrorInvalidConfiguration;
-    hipError_t e = hipFuncSetAttribute((const void *)k_weights, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (S_large > 0 && panel != 8 && panel != 16) return hipErrorInvalidValue;
+    const int pk = S_large > 0 ? panel : 0;
+    hipError_t e = hipFuncSetAttribute(weights_kernel(pk), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_weights, dim3(grid), dim3(kBS), lds, s, cx, (const Item *)items, nitems, counter, S_small,
-                       S_mid);
+    if (pk == 8)
+        hipLaunchKernelGGL(k_weights<8>, dim3(grid), dim3(kBS), lds, s, cx, (const Item *)items, nitems, counter,
+                           S_small);
+    else if (pk == 16)
+        hipLaunchKernelGGL(k_weights<16>, dim3(grid), dim3(kBS), lds, s, cx, (const Item *)items, nitems, counter,
+                           S_small);
+    else
+        hipLaunchKernelGGL(k_weights<0>, dim3(grid), dim3(kBS), lds, s, cx, (const Item *)items, nitems, counter,
+                           S_small);
     return hipGetLastError();
 }
 

@@ -856,13 +856,14 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
     std::vector<int8_t> mrows;
     const size_t isz = weights_item_bytes();
     std::vector<char> items;
-    int S_small = 0, S_mid = 0, S_large = 0;
+    int S_small = 0, S_large = 0;
     int64_t nitems = 0, nlarge = 0;
     for (auto &c : order) {
-        const int kind = c.S <= weights_small_limit() ? 0 : (c.S <= weights_mid_limit() ? 1 : 2);
+        // systems of at most weights_small_limit() unknowns: one wavefront
+        // each, matrix in LDS; larger ones: blocked, one workgroup each
+        const int kind = c.S <= weights_small_limit() ? 0 : 1;
         if (kind == 0) S_small = std::max(S_small, c.S);
-        if (kind == 1) S_mid = std::max(S_mid, c.S);
-        if (kind == 2) S_large = std::max(S_large, c.S);
+        if (kind == 1) S_large = std::max(S_large, c.S);
         const int per = kind == 0 ? 4 : 1;
         const int64_t first = (int64_t)rows.size();
         for (int32_t r : *c.rows) {
@@ -873,7 +874,7 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
             items.resize(items.size() + isz);
             weights_make_item(items.data() + items.size() - isz, kind, (int)std::min<int64_t>(per, c.rows->size() - q), first + q);
             ++nitems;
-            nlarge += kind == 2;
+            nlarge += kind == 1;
         }
     }
     ALLOC(h, h->w_can, double, (size_t)N * h->n_max);
@@ -890,18 +891,25 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
         HIPCHK(h, hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(d_m, mrows.data(), mrows.size(), hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(d_items, items.data(), items.size(), hipMemcpyHostToDevice, h->stream));
-        const int64_t slab = S_large > 0 ? (int64_t)S_large * (S_large + 1) + 32 : 0;
-        const int cand[3] = {8, 16, 32};
+        const int64_t slab = weights_slab(S_large);
+        const int cand[2] = {8, 16};
+        auto fits = [&](int pc) {
+            return weights_grid(S_small, S_large, pc) > 0 && (S_large == 0 || weights_grid(0, S_large, pc) > 0);
+        };
         // Every LARGE workgroup indexes its own scratch slab by blockIdx, so the
         // slab count must cover the largest grid launched below: the full
         // launch (all item kinds) and the panel-timing launches (LARGE items
         // only, smaller LDS footprint, hence possibly more resident groups).
         int grid_max = 0;
         for (int pc : cand) {
-            grid_max = std::max(grid_max, weights_grid(S_small, S_mid, S_large, pc));
-            if (S_large > 0) grid_max = std::max(grid_max, weights_grid(0, 0, S_large, pc));
+            grid_max = std::max(grid_max, weights_grid(S_small, S_large, pc));
+            if (S_large > 0) grid_max = std::max(grid_max, weights_grid(0, S_large, pc));
         }
         if (grid_max <= 0) return fail(h, RBF_EHIP, "weight solver does not fit on the device");
+        int panel_fit = 0;  // largest panel width whose LDS footprint fits
+        for (int pc : cand)
+            if (fits(pc)) panel_fit = pc;
+        if (panel_fit == 0) return fail(h, RBF_EHIP, "weight solver does not fit on the device");
         if (S_large > 0) ALLOC(h, scratch, double, (size_t)slab * grid_max);
         // panel width: cached choice, else time the candidates on a sample
         int panel = h->weights_panel;
@@ -909,18 +917,22 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
             char key[160];
             std::snprintf(key, sizeof key, "weights|%s|%d|%d", h->arch, dim, S_large);
             int v[1];
-            if (cache_lookup(key, v, 1)) {
+            const int forced = std::getenv("RBF_WEIGHTS_PANEL") ? std::atoi(std::getenv("RBF_WEIGHTS_PANEL")) : 0;
+            if ((forced == 8 || forced == 16) && fits(forced)) {
+                panel = forced;
+            } else if (cache_lookup(key, v, 1) && (v[0] == 8 || v[0] == 16) && fits(v[0])) {
                 panel = v[0];
             } else if (nlarge >= 4096) {
                 float best = 1e30f;
                 const int64_t sample = std::min<int64_t>(nlarge, 4 * grid_max);
                 for (int pc : cand) {
+                    if (!fits(pc)) continue;
                     HIPCHK(h, hipMemsetAsync(counter, 0, sizeof(int32_t), h->stream));
                     HIPCHK(h, hipEventRecord(h->ev0, h->stream));
                     HIPCHK(h, launch_weights_items(h->stream, dim, N, h->xyz, h->sten, h->nrow, h->n_max, d_rows, d_m,
                                                    h->type, h->normals, h->w_can, scratch, slab, pc, h->dstatus,
                                                    d_items, sample, counter,
-                                                   0, 0, S_large, weights_grid(0, 0, S_large, pc), grid_max,
+                                                   0, S_large, weights_grid(0, S_large, pc), grid_max,
                                                    nullptr));
                     HIPCHK(h, hipEventRecord(h->ev1, h->stream));
                     HIPCHK(h, hipEventSynchronize(h->ev1));
@@ -934,6 +946,7 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
                 v[0] = panel;
                 cache_store(key, v, 1);
             }
+            if (!fits(panel)) panel = panel_fit;
             h->weights_panel = panel;
         }
         rbf_status st = reset_status(h);
@@ -941,8 +954,8 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
         HIPCHK(h, hipMemsetAsync(counter, 0, sizeof(int32_t), h->stream));
         HIPCHK(h, launch_weights_items(h->stream, dim, N, h->xyz, h->sten, h->nrow, h->n_max, d_rows, d_m, h->type,
                                        h->normals, h->w_can, scratch, slab, panel, h->dstatus, d_items, nitems,
-                                       counter, S_small, S_mid,
-                                       S_large, weights_grid(S_small, S_mid, S_large, panel), grid_max, nullptr));
+                                       counter, S_small,
+                                       S_large, weights_grid(S_small, S_large, panel), grid_max, nullptr));
         DevStatus ds;
         st = read_status(h, &ds);
         dfree(h, d_rows);

@@ -134,7 +134,7 @@ struct rbf_handle {
     rbf::SweepCfg cfg32;  // FP32 inner sweeps
     rbf::SweepCfg cfgT;   // transposed gather of the adjoint
     bool tunedT = false;
-    int weights_panel = 32;
+    int weights_panel = 16;
     double last_sweep_sec = 0.0;
     int64_t last_sweeps = 0;
 
@@ -179,16 +179,18 @@ hipError_t launch_knn_query(hipStream_t s, const CellGrid &g, int64_t N, const d
                             DevStatus *status);
 
 // ---------------------------------------------------------------- weights
+// Row stride (doubles) of a LARGE system's slab: S + 1 columns rounded up to 4.
+__host__ __device__ constexpr int blocked_ld(int S) { return (S + 1 + 3) & ~3; }
+int64_t weights_slab(int S_large);
 int weights_small_limit();
-int weights_mid_limit();
-int weights_grid(int S_small, int S_mid, int S_large, int panel);
+int weights_grid(int S_small, int S_large, int panel);
 size_t weights_item_bytes();
 void weights_make_item(void *dst, int kind, int count, int64_t first);
 hipError_t launch_weights_items(hipStream_t s, int dim, int64_t N, const double *xyz, const int32_t *sten,
                                 const int16_t *nrow, int32_t n_max, const int32_t *rows, const int8_t *mrow,
                                 const int8_t *type, const double *normals, double *w_out, double *scratch,
                                 int64_t slab, int panel, DevStatus *status, const void *items, int64_t nitems,
-                                int32_t *counter, int S_small, int S_mid, int S_large, int grid, int nslabs,
+                                int32_t *counter, int S_small, int S_large, int grid, int nslabs,
                                 size_t *lds_used);
 
 // ---------------------------------------------------------------- sweep family

@@ -89,6 +89,32 @@ def test_weights_match_oracle(dim, side, m, n):
     assert (wg[~I] == 0).all()
 
 
+@pytest.mark.parametrize("m,n", [(6, 168), (4, 140), (2, 256)])
+def test_weights_panel_widths_agree_bitwise(m, n, monkeypatch):
+    """Systems above 112 unknowns are factored by panels of 8 or 16 columns;
+    both widths perform the same operations in the same order, so the
+    weights are bitwise equal (and match the oracle within the bar)."""
+    xyz, typ = ri.jittered_grid(3, 11, 0.3, 40 + m)
+    got = {}
+    for panel in (8, 16):
+        monkeypatch.setenv("RBF_WEIGHTS_PANEL", str(panel))
+        p = _problem()
+        p.set_nodes(xyz, typ)
+        p.build_stencils(n)
+        p.compute_weights(m)
+        got[panel] = p.get_weights()
+        p.close()
+    assert np.array_equal(got[8], got[16])
+    I = typ == 0
+    rows = np.nonzero(I)[0][::7]
+    idx = oracle.knn(xyz, n, rows)
+    w = oracle.weights(xyz, idx, rows, m=m)[0]
+    rel = _rel_rows(got[16][rows, :n], w)
+    print(f"m={m} n={n}: panels 8 / 16 bitwise equal; max row-relative difference to the oracle {rel:.2e}, "
+          f"bitwise equal rows {np.mean((got[16][rows, :n] == w).all(axis=1)):.3f}")
+    assert rel <= 1e-10
+
+
 def test_weights_mixed_orders_one_launch():
     """Per-node orders (2 near the boundary, 4 and 6 inside) in one launch."""
     side = 14
