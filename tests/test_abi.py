@@ -110,11 +110,16 @@ def test_shipped_tuning_file_is_valid():
         pytest.skip("no shipped tuning file")
     d = json.load(open(path))
     assert d
+    # the library's cache writer rewrites the file line by line: each entry
+    # (key and whole value list) must sit on one line
+    body = [l for l in open(path).read().splitlines() if l.strip() not in ("{", "}", "")]
+    assert len(body) == len(d)
+    assert all(l.strip().startswith('"') and l.rstrip(",").endswith("]") for l in body)
     for key, v in d.items():
         kind = key.split("|")[0]
         assert kind in ("sweep", "sweep32", "sweepT", "weights"), key
         if kind == "weights":
-            assert v[0] in (8, 16, 32)
+            assert v[0] in (8, 16)
             continue
         assert len(v) in (6, 7, 8), key
         assert v[0] in (2, 4, 8) and v[1] in (4, 8, 16, 32), key
