@@ -6,7 +6,7 @@
 //   SMALL  4 systems with S = n + M <= 40, one wavefront each, matrix in LDS;
 //   LARGE  1 system with larger S on the whole workgroup: the matrix lives in
 //          a per-workgroup scratch slab and is factored by panels of 8 or 16
-//          columns staged in LDS.
+//          columns (rows in registers, or staged in LDS when S > 256).
 // Items are queued largest first so the tail of the launch is short.
 //
 // Every path performs, element by element, the same floating-point
@@ -326,13 +326,15 @@ __device__ void solve_lds_item(const WCtx &cx, const Item &it, char *lds, int S_
 // two aligned 16-byte loads), factored by panels of PB columns staged in LDS.
 //
 // Per panel:
-//   1. stage the panel (rows k0.., PB columns) in LDS, row stride PB + 1 so a
-//      column read by 64 lanes hits distinct banks;
-//   2. factor it: per step, the pivot is known from the previous step; the
-//      row swap (columns != kk) and the scaling of column kk touch disjoint
-//      entries and share one barrier; the rank-1 update of column kk + 1 and
-//      the search for the next pivot are done by wavefront 0 while the other
-//      wavefronts update the remaining columns (two barriers per step);
+//   1. factor it, the rows in registers (factor_panel_regs, S <= 256), else
+//      staged in LDS with row stride PB + 1 (a column read by 64 lanes hits
+//      distinct banks): per step, the pivot is known from the previous step;
+//      the row swap (columns != kk) and the scaling of column kk touch
+//      disjoint entries and share one barrier; the rank-1 update of column
+//      kk + 1 and the search for the next pivot are done by wavefront 0 while
+//      the other wavefronts update the remaining columns (two barriers per
+//      step); either way the factored panel ends in LDS (Lp);
+//   2. write the pivot rows back, and let wavefront 0 replay the swaps;
 //   3. per trailing column, one pass: gather the rows the panel's swaps touch
 //      (independent loads), finish the pivot rows (U12) in registers, store;
 //   4. trailing update in 4x4 register tiles, the next tile's loads issued
