@@ -644,8 +644,12 @@ static rbf_status make_ell(rbf_handle *h, int64_t row0, int64_t nrows, const std
 // FP64 sweeps, 1: FP32).
 static void sweep_key(const rbf_handle *h, int prec, char *key, size_t len) {
     const Ell &e = h->ell;
-    std::snprintf(key, len, "%s|%s|L%d|%" PRId64 "|%" PRId64 "|%d|c%" PRId64, prec ? "sweep32" : "sweep", h->arch,
-                  e.layout, h->N_int, e.elems, e.max_len, e.coded_slices);
+    // problems with Neumann rows sweep in two parts around the Neumann update:
+    // their own key, even where the interior operator has the same shape
+    char neu[32] = "";
+    if (h->N_neu > 0) std::snprintf(neu, sizeof neu, "|nn%" PRId64, h->N_neu);
+    std::snprintf(key, len, "%s|%s|L%d|%" PRId64 "|%" PRId64 "|%d|c%" PRId64 "%s", prec ? "sweep32" : "sweep", h->arch,
+                  e.layout, h->N_int, e.elems, e.max_len, e.coded_slices, neu);
 }
 
 // Apply cached shape values v[8] to c.

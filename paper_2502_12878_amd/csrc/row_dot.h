@@ -266,6 +266,43 @@ __device__ __forceinline__ int32_t code_col(uint32_t c, int32_t segreg) {
     return __builtin_amdgcn_ds_bpermute((int)((c >> 10) & 0x3cu), segreg) + (int32_t)(c & 0xfffu);
 }
 
+// The last len - kt < U entries of a coded row (kt a multiple of 4): all
+// their code and weight vectors are requested at once, then the gathers,
+// then the products in entry order (the order of the one-pair-at-a-time
+// loop, so the result is the same bit for bit).
+template <typename T, int U, bool NT, class X>
+__device__ __forceinline__ T coded_tail(const u16x4 *cp, const typename Vec2<T>::type *wp, int32_t segreg,
+                                        const X &x, int kt, int len, T acc) {
+    typedef typename Vec2<T>::type V;
+    if (kt >= len) return acc;
+    u16x4 c[U / 4];
+    V ww[U / 2];
+#pragma unroll
+    for (int q = 0; q < U / 4; ++q)
+        if (kt + 4 * q < len) c[q] = ld_op<NT>(cp + ((kt >> 2) + q) * kSlice);
+#pragma unroll
+    for (int q = 0; q < U / 2; ++q)
+        if (kt + 2 * q < len) ww[q] = ld_op<NT>(wp + ((kt >> 1) + q) * kSlice);
+    T xx[U];
+#pragma unroll
+    for (int q = 0; q < U / 4; ++q)
+        if (kt + 4 * q < len) {
+            xx[4 * q] = x[code_col(c[q].x, segreg)];
+            xx[4 * q + 1] = x[code_col(c[q].y, segreg)];
+            if (kt + 4 * q + 2 < len) {
+                xx[4 * q + 2] = x[code_col(c[q].z, segreg)];
+                xx[4 * q + 3] = x[code_col(c[q].w, segreg)];
+            }
+        }
+#pragma unroll
+    for (int q = 0; q < U / 2; ++q)
+        if (kt + 2 * q < len) {
+            acc = fma(ww[q].x, xx[2 * q], acc);
+            acc = fma(ww[q].y, xx[2 * q + 1], acc);
+        }
+    return acc;
+}
+
 // Compressed rows (Ell::code): 4 codes per 8-byte vector, weights as pairs
 // (layout 1); len is even, codes are padded to a multiple of 4.
 template <typename T, int U, bool NT = true>
@@ -300,14 +337,7 @@ struct RowDotC {
                 acc = fma(ww[q].y, xx[2 * q + 1], acc);
             }
         }
-        for (; k < len; k += 2) {
-            const u16x4 c = ld_op<NT>(cp + (k >> 2) * kSlice);
-            const V ww = ld_op<NT>(wp + (k >> 1) * kSlice);
-            const uint32_t c0 = (k & 2) ? c.z : c.x, c1 = (k & 2) ? c.w : c.y;
-            acc = fma(ww.x, x[code_col(c0, segreg)], acc);
-            acc = fma(ww.y, x[code_col(c1, segreg)], acc);
-        }
-        return acc;
+        return coded_tail<T, U, NT>(cp, wp, segreg, x, k, len, acc);
     }
 };
 
@@ -359,14 +389,7 @@ struct RowDotCP {
                 acc = fma(wc[q].y, xx[2 * q + 1], acc);
             }
         }
-        for (int k = groups * U; k < len; k += 2) {
-            const u16x4 c = ld_op<NT>(cp + (k >> 2) * kSlice);
-            const V ww = ld_op<NT>(wp + (k >> 1) * kSlice);
-            const uint32_t c0 = (k & 2) ? c.z : c.x, c1 = (k & 2) ? c.w : c.y;
-            acc = fma(ww.x, x[code_col(c0, segreg)], acc);
-            acc = fma(ww.y, x[code_col(c1, segreg)], acc);
-        }
-        return acc;
+        return coded_tail<T, U, NT>(cp, wp, segreg, x, groups * U, len, acc);
     }
 };
 
