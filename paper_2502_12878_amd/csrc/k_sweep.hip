@@ -36,11 +36,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
     unsigned long long bits = 0;
     if (local < nslices) {
         const int len = slice_len[slice];
-        const double acc = row_dot<double, U, LAYOUT>(cs, slice_ptr, idx, w, BufGather<double>(u_old, ncols), slice, lane, len);
         const int64_t row = slice * kSlice + lane;
-        if (row < N_int) {
-            const double rho = acc - f[row];
-            u_new[row] = u_old[row] + dt * rho;
+        const bool live = row < N_int;
+        const double fr = live ? f[row] : 0.0;  // requested with the slice's descriptors
+        const double ur = live ? u_old[row] : 0.0;
+        const double acc = row_dot<double, U, LAYOUT>(cs, slice_ptr, idx, w, BufGather<double>(u_old, ncols), slice, lane, len);
+        if (live) {
+            const double rho = acc - fr;
+            u_new[row] = ur + dt * rho;
             bits = (unsigned long long)__double_as_longlong(fabs(rho));
         }
     }
@@ -57,9 +60,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f32(
     const int lane = threadIdx.x & 63;
     if (slice >= nslices) return;
     const int len = slice_len[slice];
-    const float acc = row_dot<float, U, LAYOUT>(cs, slice_ptr, idx, w, BufGather<float>(e_old, ncols), slice, lane, len);
     const int64_t row = slice * kSlice + lane;
-    if (row < N_int) e_new[row] = e_old[row] + dt * (acc - r[row]);
+    const bool live = row < N_int;
+    const float rr = live ? r[row] : 0.0f;
+    const float er = live ? e_old[row] : 0.0f;
+    const float acc = row_dot<float, U, LAYOUT>(cs, slice_ptr, idx, w, BufGather<float>(e_old, ncols), slice, lane, len);
+    if (live) e_new[row] = er + dt * (acc - rr);
 }
 
 // Lu (and, with f, max |Lu - f| into slot).

@@ -101,17 +101,21 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f32q(
     const int64_t slice = slice_index<WAVES>(nslices, order);
     const int lane = threadIdx.x & 63;
     if (slice >= nslices) return;
+    // the slice's descriptors and the row's r and e in one round trip
     const int len = slice_len[slice];
+    const int8_t coded = cs.cmode[slice];
+    const int32_t segreg = cs.segbase[slice * kSegs + (lane & (kSegs - 1))];
+    const int64_t cbase = cs.cptr[slice];
+    const int64_t sbase = slice_ptr[slice];
+    const int64_t row = slice * kSlice + lane;
+    const bool live = row < N_int;
+    const float rr = live ? r[row] : 0.0f;
+    const float er = live ? e_old[row] : 0.0f;
     const BufGather<float> x(e_old, ncols);
     float acc;
-    if (cs.cmode[slice]) {
-        const int32_t segreg = cs.segbase[slice * kSegs + (lane & (kSegs - 1))];
-        acc = RowDotCQ<U, NT, PIPE>::run(cs.code + cs.cptr[slice], wq + cs.cptr[slice], segreg, x, lane, len);
-    } else {
-        acc = RowDot<float, U, PIPE ? 2 : 1>::run(idx, w, x, slice_ptr[slice], lane, len);
-    }
-    const int64_t row = slice * kSlice + lane;
-    if (row < N_int) e_new[row] = e_old[row] + dt * (acc - r[row]);
+    if (coded) acc = RowDotCQ<U, NT, PIPE>::run(cs.code + cbase, wq + cbase, segreg, x, lane, len);
+    else acc = RowDot<float, U, PIPE ? 2 : 1>::run(idx, w, x, sbase, lane, len);
+    if (live) e_new[row] = er + dt * (acc - rr);
 }
 
 template <int WV, int UN, int LY>

@@ -415,14 +415,19 @@ __device__ __forceinline__ T row_dot(const Codes &cs, const int64_t *__restrict_
     if constexpr (LAYOUT >= 3) {
         constexpr bool NT = LAYOUT <= 4;                    // 5 / 6: ordinary stream loads
         constexpr bool PIPE = LAYOUT == 4 || LAYOUT == 6;
-        if (cs.cmode[slice]) {
-            const int32_t segreg = cs.segbase[slice * kSegs + (lane & (kSegs - 1))];
+        // the slice's descriptors in one round trip (segbase and cptr exist,
+        // unused, for slices without codes)
+        const int8_t coded = cs.cmode[slice];
+        const int32_t segreg = cs.segbase[slice * kSegs + (lane & (kSegs - 1))];
+        const int64_t cbase = cs.cptr[slice];
+        const int64_t sbase = slice_ptr[slice];
+        if (coded) {
             if constexpr (PIPE)
-                return RowDotCP<T, U, NT>::run(cs.code + cs.cptr[slice], segreg, w + slice_ptr[slice], x, lane, len);
+                return RowDotCP<T, U, NT>::run(cs.code + cbase, segreg, w + sbase, x, lane, len);
             else
-                return RowDotC<T, U, NT>::run(cs.code + cs.cptr[slice], segreg, w + slice_ptr[slice], x, lane, len);
+                return RowDotC<T, U, NT>::run(cs.code + cbase, segreg, w + sbase, x, lane, len);
         }
-        return RowDot<T, U, PIPE ? 2 : 1>::run(idx, w, x, slice_ptr[slice], lane, len);
+        return RowDot<T, U, PIPE ? 2 : 1>::run(idx, w, x, sbase, lane, len);
     } else {
         return RowDot<T, U, LAYOUT>::run(idx, w, x, slice_ptr[slice], lane, len);
     }
