@@ -416,6 +416,34 @@ __device__ __forceinline__ void wave_argmax(double &best, int &p, double &val) {
     }
 }
 
+// Largest 64-bit key over a wavefront, returned to every lane.  Within each
+// row of 16 lanes by DPP moves (swap neighbours, swap pairs, rotate by 4 and
+// by 8: each lane then holds its row's maximum), then across the four rows
+// through readlane.
+__device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long v, unsigned long long o) {
+    return o > v ? o : v;
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)v, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+    v = dpp_max_u64(v, dpp_u64<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+    v = dpp_max_u64(v, dpp_u64<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+    v = dpp_max_u64(v, dpp_u64<0x124>(v));  // row_ror:4
+    v = dpp_max_u64(v, dpp_u64<0x128>(v));  // row_ror:8
+    unsigned long long m = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 16 * r);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 16 * r);
+        m = dpp_max_u64(m, ((unsigned long long)hi << 32) | lo);
+    }
+    return m;
+}
+
 // Panel factorization with the panel's rows in registers, thread t holding
 // row k0 + t (needs S <= kBS).  Per step, one barrier: each wavefront puts its
 // candidate pivot row (first row of largest |a|) and the current row kk in
@@ -440,12 +468,7 @@ __device__ bool factor_panel_regs(const BlockedLds<PB> &L, const double *A, int 
         const double cv = a[kk];
         unsigned long long key = 0;
         if (mine && t >= kk && cv == cv) key = (unsigned long long)__double_as_longlong(fabs(cv));
-        unsigned long long wmax = key;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const unsigned long long o = __shfl_xor(wmax, off, 64);
-            wmax = o > wmax ? o : wmax;
-        }
+        const unsigned long long wmax = wave_max_u64(key);
         const int cl = __ffsll((long long)__ballot(key == wmax)) - 1;
         if (lane == cl) {
             L.skey[buf * NW + wave] = wmax;
