@@ -121,6 +121,35 @@ def time_to_error(s, target, inner=500, max_steps=2_000_000):
     return out
 
 
+def run_cube1m_fp32(steps=2000, warmup=500, inner=500):
+    """FP32 inner sweeps of the mixed mode on cube1M, m = 4: outer passes of
+    `inner` FP32 steps, each after one FP64 residual.  Device time per inner
+    step (the outer residuals included: one per `inner` steps) and the stream
+    rates against 8n + 12 algorithmic bytes and against the bytes as stored."""
+    from paper_2502_12878_amd import RBF_MODE_MIXED
+    s = setup_problem(4, keep_fp32=True)
+    p, wl = s["p"], s["wl"]
+    nint = int((s["typ"] == 0).sum())
+    u = s["u0"].clone()
+    st, _ = p.iterate(s["f"], u, wl.dt, warmup, 0.0, inner, mode=RBF_MODE_MIXED, inner_steps=inner)
+    assert st == 0, st
+    u = s["u0"].clone()
+    st, rep = p.iterate(s["f"], u, wl.dt, steps, 0.0, inner, mode=RBF_MODE_MIXED, inner_steps=inner)
+    assert st == 0 and rep["steps"] == steps, (st, rep)
+    per = rep["seconds"] / rep["steps"]
+    info = p.operator_info()
+    alg = (8 * wl.n + 12) * nint
+    out = {"workload": f"cube1M_fp32: 3D 100^3 jittered grid (seed 1), m=4, n={wl.n}, FP32 inner sweeps of {inner} "
+                       f"steps inside the FP64 residual correction",
+           "steps": rep["steps"], "device_s": round(rep["seconds"], 4), "ms_per_inner_step": 1e3 * per,
+           "node_updates_per_s": nint / per, "alg_bytes_per_update": 8 * wl.n + 12, "alg_GBps": alg / per / 1e9,
+           "hbm_frac": alg / per / 1e9 / PEAK_HBM_GBS, "format_bytes_per_sweep": info["stream_bytes_f32"],
+           "format_GBps": info["stream_bytes_f32"] / per / 1e9,
+           "sweep_shape": {k[4:]: v for k, v in info.items() if k.startswith("f32_")}}
+    p.close()
+    return out
+
+
 def cpu_baseline(budget_s=10.0):
     """The oracle's OpenMP sweep on a bounded sample of the workload: the same
     generator and parameters (3D, jitter 0.3h, seed 1, m = 4, n = 70) on a
@@ -575,8 +604,8 @@ def main():
     ap.add_argument("--tte-target", type=float, default=1e-6)
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--workload", default="cube1M",
-                    choices=["cube1M", "cube8M", "cube4M_bands", "cube2M_adjoint", "support_sweep", "order_scan",
-                             "mixed_bc"],
+                    choices=["cube1M", "cube1M_fp32", "cube8M", "cube4M_bands", "cube2M_adjoint", "support_sweep",
+                             "order_scan", "mixed_bc"],
                     help="cube1M: the benchmark line; the others print their own measurement line")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32_refine"], help="cube8M: iteration mode")
     args = ap.parse_args()
@@ -604,6 +633,8 @@ def main():
             out = run_order_scan()
         elif args.workload == "mixed_bc":
             out = run_mixed_bc()
+        elif args.workload == "cube1M_fp32":
+            out = run_cube1m_fp32()
         else:
             out = run_cube2m_adjoint()
         out["device"] = torch.cuda.get_device_name(0)
