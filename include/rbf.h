@@ -139,7 +139,7 @@ rbf_status rbf_build_stencils(rbf_handle *h, int32_t n_uniform, const int16_t *n
  * 3|y_k| ((0 - y_k) . nv) and nv_a for the monomial y_a, w = x/s.
  * m_uniform: order for every node, or -1 with m_per_node_dev ([N] int8).
  * keep_fp32: also keep an FP32 copy (needed by the mixed-precision mode).
- * Systems larger than 112 unknowns are factored by panels of 8 or 16
+ * Systems larger than 40 unknowns are factored by panels of 8 or 16
  * columns; the panel width is read from the tuning cache (key
  * weights|arch|dim|S), else timed on a sample when there are at least 4096
  * such systems, else 16; RBF_WEIGHTS_PANEL=8 or 16 fixes it.  Every width
