@@ -115,6 +115,34 @@ def test_weights_panel_widths_agree_bitwise(m, n, monkeypatch):
     assert rel <= 1e-10
 
 
+def test_weights_all_solver_paths_in_one_launch():
+    """One launch with systems of 30 unknowns (one wavefront each, matrix in
+    LDS), 105 unknowns (panel rows in registers) and 266 unknowns (more than
+    256 rows: panels staged in LDS), interleaved over the nodes."""
+    xyz, typ = ri.jittered_grid(3, 11, 0.3, 21)
+    N = len(typ)
+    interior = np.nonzero(typ == 0)[0]
+    n = np.full(N, 20, dtype=np.int16)
+    m = np.full(N, 2, dtype=np.int8)
+    n[interior[1::3]], m[interior[1::3]] = 70, 4
+    n[interior[2::7]], m[interior[2::7]] = 256, 2
+    S = n + np.where(m == 4, 35, 10)
+    assert {30, 105, 266} <= set(S[interior].tolist())
+    p = _problem()
+    p.set_nodes(xyz, typ)
+    p.build_stencils(n_per_node=n)
+    p.compute_weights(m_per_node=m)
+    wg = p.get_weights()
+    for nn, mm in ((20, 2), (70, 4), (256, 2)):
+        rows = interior[(n[interior] == nn) & (m[interior] == mm)][::3]
+        idx = oracle.knn(xyz, nn, rows)
+        w = oracle.weights(xyz, idx, rows, m=mm)[0]
+        rel = _rel_rows(wg[rows, :nn], w)
+        print(f"n={nn} m={mm}: {len(rows)} rows, max row-relative difference {rel:.2e}, "
+              f"bitwise equal rows {np.mean((wg[rows, :nn] == w).all(axis=1)):.3f}")
+        assert rel <= 1e-10
+
+
 def test_weights_mixed_orders_one_launch():
     """Per-node orders (2 near the boundary, 4 and 6 inside) in one launch."""
     side = 14
