@@ -387,6 +387,35 @@ def test_singular_supports_reported():
     assert ei.value.status == RBF_ESINGULAR
 
 
+@pytest.mark.parametrize("m,n", [(4, 70), (2, 256)])
+def test_singular_blocked_systems_reported(m, n):
+    """Two nodes at the same place make every system whose support holds both
+    singular.  Systems of 105 unknowns (panel rows in registers) and of 266
+    (panels staged in LDS) take the blocked path; the status is ESINGULAR and
+    the node reported is the lowest singular centre, the one the oracle's
+    elimination stops at."""
+    from paper_2502_12878_amd import RbfError, RBF_ESINGULAR
+    side = 11
+    xyz, typ = ri.jittered_grid(3, side, 0.3, 31)
+    a = 5 + side * 5 + side * side * 5
+    b = a + 1
+    assert typ[a] == 0 and typ[b] == 0
+    xd = xyz.copy()
+    xd[:, b] = xd[:, a]
+    p = _problem()
+    p.set_nodes(xd, typ)
+    p.build_stencils(n)
+    with pytest.raises(RbfError) as ei:
+        p.compute_weights(m)
+    assert ei.value.status == RBF_ESINGULAR
+    rows = np.nonzero(typ == 0)[0]
+    idx = oracle.knn(xd, n, rows)
+    both = rows[(idx == a).any(axis=1) & (idx == b).any(axis=1)]
+    assert len(both) > 0
+    _, _, st, bad = oracle.weights(xd, oracle.knn(xd, n, both), both, m=m, raise_on_singular=False)
+    assert st == 3 and f"node {bad}" in str(ei.value)
+
+
 def test_invalid_arguments_rejected():
     from paper_2502_12878_amd import RbfError, RBF_EINVAL
     p = _problem()
