@@ -683,6 +683,15 @@ def main():
         info = s["p"].operator_info()
         tte["fp32_sweep_shape"] = {k[4:]: v for k, v in info.items() if k.startswith("f32_")}
         tte["fp32_format_bytes_per_sweep"] = info["stream_bytes_f32"]
+        r = tte["fp32_refine"]
+        if r["steps"]:
+            # device time per inner step of the refinement run (its outer
+            # FP64 residuals included, one per 500 steps) against 8n + 12 bytes
+            per32 = r["device_s"] / r["steps"]
+            alg32 = (8 * wl.n + 12) * entry["interior_nodes"]
+            tte["fp32_ms_per_inner_step"] = round(1e3 * per32, 5)
+            tte["fp32_alg_GBps"] = round(alg32 / per32 / 1e9, 1)
+            tte["fp32_hbm_frac"] = round(alg32 / per32 / 1e9 / PEAK_HBM_GBS, 4)
     cpu = None if args.no_cpu else cpu_baseline()
     out = {"metric": "sweep node-updates/s + HBM GB/s; time to L-inf err 1e-6, FP32+refine vs FP64",
            "value": entry["node_updates_per_s"], "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps,
