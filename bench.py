@@ -23,6 +23,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# FP64 vector instructions per second on MI355X (78.6 TFLOP/s counts an FMA as
+# two operations; a separate multiply or subtract is one instruction)
+PEAK_FP64_OPS = 39.3e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -291,6 +294,12 @@ def run_cube4m_bands(steps=1000):
                         "(<3h, <6h, else), n=2M", "classes": classes, "interior_nodes": nint,
             "stencils_s": round(t1 - t0, 3), "weights_s": round(t2 - t1, 3),
             "weights_gflops": round(flops / (t2 - t1) / 1e9, 1), "weights_flop_total": flops,
+            # the solver's operations are separate FP64 multiplies and
+            # subtracts (the oracle's order), each one vector instruction:
+            # the ceiling is the FP64 vector rate counted per instruction
+            "weights_roofline": {"bound": "fp64 vector ALU (latency of the pivot chain in practice)",
+                                 "achieved": round(flops / (t2 - t1) / 1e12, 3), "peak": PEAK_FP64_OPS / 1e12,
+                                 "unit": "Top/s", "frac": round(flops / (t2 - t1) / PEAK_FP64_OPS, 4)},
             "sweep_kernel_ms": round(1e3 * per_sweep, 4), "node_updates_per_s": nint / per_sweep,
             "sweep_alg_GBps": round(alg_bytes / per_sweep / 1e9, 1),
             "sweep_hbm_frac": round(alg_bytes / per_sweep / 1e9 / PEAK_HBM_GBS, 4), "res_final": rep["res_final"]}
