@@ -1585,6 +1585,7 @@ static rbf_status tune_transpose(rbf_handle *h) {
             for (int un : {4, 8, 16})
                 for (int rm : {0, 1})
                     for (int pl : {0, 1})
+                    for (int zz : {0, 1})
                     for (int cd : {0, 1})
                     for (int tp : {0, 1}) {
                         if ((cd && !e.cmode) || (tp && !cd)) continue;
@@ -1593,6 +1594,7 @@ static rbf_status tune_transpose(rbf_handle *h) {
                         c.unroll = un;
                         c.xcd_remap = rm;
                         c.pipeline = pl;
+                        c.zigzag = zz;
                         c.codes = cd;
                         c.temporal = tp;
                         auto launch = [&](int r) {
