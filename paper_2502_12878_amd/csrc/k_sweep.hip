@@ -125,17 +125,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_adjoint_gather(
     const int lane = threadIdx.x & 63;
     if (slice >= nslices) return;
     const int len = slice_len[slice];
-    const int64_t row = slice * kSlice + lane;
-    const bool live = row < N_int;
-    // the row's own values are requested with the slice's descriptors
-    const double lr = live ? lam_old[row] : 0.0;
-    const double ar = live ? acc[row] : 0.0;
     const double s =
         row_dot<double, U, LAYOUT>(cs, slice_ptr, idx, w, BufGather<double>(lam_old, ncols), slice, lane, len);
-    if (live) {
-        const double l = lr + dt * s;
+    const int64_t row = slice * kSlice + lane;
+    if (row < N_int) {
+        const double l = lam_old[row] + dt * s;
         lam_new[row] = l;
-        acc[row] = ar + l;
+        acc[row] += l;
     }
 }
 
