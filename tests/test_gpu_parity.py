@@ -313,6 +313,27 @@ def test_transpose_gather_repeatable_and_matches_scatter(monkeypatch):
     assert np.abs(g1.cpu().numpy() - go).max() <= 1e-11 * np.abs(go).max()
 
 
+def test_transpose_gather_shapes_bitwise_identical(monkeypatch):
+    """The adjoint's transposed gather sums each row in one order in every
+    shape (workgroup size, unroll, XCD order, pipelining, zig-zag, codes,
+    temporal loads): gradients are bitwise equal across shapes, including
+    checkpoint segments of odd length, and match the oracle."""
+    rng = np.random.default_rng(21)
+    res = []
+    for shape in ("2,4,0,0,0,0", "4,16,0,1,1,1,1", "8,8,1,1,1,1,0", "4,16,1,0,1,1,1", "2,8,0,1,0,1,1"):
+        monkeypatch.setenv("RBF_SWEEP_SHAPE", shape)
+        s = _setup_pair(3, 14, 4, 70, 23)
+        if not res:
+            gK = rng.standard_normal(len(s["typ"]))
+        g = s["p"].adjoint_f(s["dev"](gK), 201, 67, s["dt"]).cpu().numpy()
+        res.append(g)
+        s["p"].close()
+    for g in res[1:]:
+        assert np.array_equal(g, res[0])
+    go = s["op"].adjoint_f(s["dt"], 201, gK)
+    assert np.abs(res[0] - go).max() <= 1e-11 * np.abs(go).max()
+
+
 def test_forward_checkpoints_resume_bitwise():
     s = _setup_pair(2, 19, 2, 12, 9)
     p, dev = s["p"], s["dev"]
