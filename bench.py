@@ -420,6 +420,71 @@ def run_support_sweep(m=2, sizes=(20, 30, 40, 60, 80, 100, 130, 168), steps=1000
             "fit_ms_per_byte_per_row": a, "fit_ms_offset": b}
 
 
+def run_square10k(chunks=(100, 1000, 5000)):
+    """The 2D 10k-node case (100^2 jittered grid, seed 0, m = 2, n = 12), a
+    cache- and launch-bound problem rather than a bandwidth point.  At the
+    literal step 0.9 dt_max the iteration diverges: the step where the GPU
+    and the oracle stop is reported.  At 0.15 dt_max, 20,000 steps run on the
+    GPU (graph chunks of several lengths, each graph built before timing) and
+    for real in the oracle's sequential sweep; errors against the exact
+    solution (L-inf and the mean absolute error over all nodes) and the
+    GPU-oracle difference are reported."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import rbf_inputs as ri
+    from paper_2502_12878_amd import Problem
+    out = {"workload": "square10k: 2D 100^2 jittered grid (seed 0), m=2, n=12, 20,000 steps"}
+    for name in ("square10k", "square10k_stable"):
+        wl = ri.workload(name)
+        xyz, typ = wl.nodes()
+        u_ex, f, g, u0 = ri.manufactured(2, xyz, typ)
+        steps = wl.extra["steps"]
+        p = Problem(0)
+        xd, td = p.build_nodes(2, wl.side, wl.jitter, wl.seed)
+        p.set_nodes(xd, td)
+        p.build_stencils(wl.n)
+        p.compute_weights(wl.m)
+        p.autotune()
+        fd, uref = _dev(f), _dev(u_ex)
+        idx, w = oracle.setup(xyz, typ, wl.n, m=wl.m)
+        op = oracle.Operator(typ, idx, w)
+        t0 = time.perf_counter()
+        uo, rep_o, st_o = op.iterate(f, wl.dt, u0, steps, 0.0, 1000)
+        cpu_s = time.perf_counter() - t0
+        if name == "square10k":
+            u = _dev(u0)
+            st, rep = p.iterate(fd, u, wl.dt, steps, 0.0, 1000, u_ref=uref)
+            out["literal_0.9dt_max"] = {"status": st, "diverged_step": rep["diverged_step"],
+                                        "oracle_status": st_o, "oracle_diverged_step": rep_o["diverged_step"]}
+            p.close()
+            continue
+        runs = []
+        for chunk in chunks:
+            u = _dev(u0)
+            p.iterate(fd, u, wl.dt, chunk, 0.0, chunk, u_ref=uref)  # builds the chunk's graph
+            u = _dev(u0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, rep = p.iterate(fd, u, wl.dt, steps, 0.0, chunk, u_ref=uref)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            runs.append({"chunk": chunk, "status": st, "wall_s": round(wall, 4),
+                         "us_per_step": round(1e6 * wall / steps, 3), "steps_per_s": round(steps / wall, 1)})
+            _progress(f"square10k chunk {chunk}: {1e6 * wall / steps:.3f} us per step")
+        ug = u.cpu().numpy()
+        nint = int((typ == 0).sum())
+        best = min(r["wall_s"] for r in runs)
+        out["stable_0.15dt_max"] = {
+            "interior_nodes": nint, "runs": runs, "best_steps_per_s": round(steps / best, 1),
+            "best_node_updates_per_s": nint * steps / best, "err_inf": rep["err_inf"],
+            "err_mean_abs": rep["err_mean_abs"], "rel_diff_vs_oracle": float(np.abs(ug - uo).max() / np.abs(uo).max()),
+            "oracle_sequential_s": round(cpu_s, 3), "oracle_steps_per_s": round(steps / cpu_s, 1)}
+        p.close()
+    return out
+
+
 def _converge(p, fd, u, dt, uref, tol_rel, max_steps, chunk=500, stall=10):
     """Iterate to relative residual `tol_rel` (or a 10-chunk stall at the
     rounding floor); returns the report with the final errors."""
@@ -614,7 +679,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--workload", default="cube1M",
                     choices=["cube1M", "cube1M_fp32", "cube8M", "cube4M_bands", "cube2M_adjoint", "support_sweep",
-                             "order_scan", "mixed_bc"],
+                             "order_scan", "mixed_bc", "square10k"],
                     help="cube1M: the benchmark line; the others print their own measurement line")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32_refine"], help="cube8M: iteration mode")
     args = ap.parse_args()
@@ -644,6 +709,8 @@ def main():
             out = run_mixed_bc()
         elif args.workload == "cube1M_fp32":
             out = run_cube1m_fp32()
+        elif args.workload == "square10k":
+            out = run_square10k()
         else:
             out = run_cube2m_adjoint()
         out["device"] = torch.cuda.get_device_name(0)
