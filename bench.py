@@ -199,11 +199,14 @@ def _dev(a):
     return torch.tensor(a, dtype=torch.float64, device="cuda")
 
 
-def run_cube8m(mode_name, target, piece_steps=40000, max_steps=3_000_000):
+def run_cube8m(mode_name, target, piece_steps=40000, max_steps=3_000_000, cpu_sweeps=3):
     """Time to L-inf error `target` against the exact solution on the 8M-node
     cube (m = 4, n = 70), FP64 or FP32 inner sweeps with FP64 refinement; the
     error is checked every 500 steps in both modes.  Runs in pieces of
-    `piece_steps` steps (the state is just u) so progress is printed."""
+    `piece_steps` steps (the state is just u) so progress is printed.  In FP64
+    mode the oracle's OpenMP sweep is then timed on the same operator (copied
+    to the host) for `cpu_sweeps` steps, and the CPU time to the target is
+    extrapolated as the GPU's step count times that time per step."""
     import torch
 
     import rbf_inputs as ri
@@ -241,7 +244,26 @@ def run_cube8m(mode_name, target, piece_steps=40000, max_steps=3_000_000):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     sample = u[:: 1009].cpu().numpy()
+    cpu = None
+    if mode == RBF_MODE_FP64 and cpu_sweeps > 0:
+        import oracle
+        _progress("cube8M: timing the oracle's OpenMP sweep on the same operator")
+        op = oracle.Operator(typ_h, p.get_stencils(), p.get_weights())
+        threads = len(os.sched_getaffinity(0))
+        a, b = u0.copy(), u0.copy()
+        op.sweep_omp(f, wl.dt, a, b, threads)  # untimed first sweep
+        t1 = time.perf_counter()
+        for _ in range(cpu_sweeps):
+            op.sweep_omp(f, wl.dt, a, b, threads)
+            a, b = b, a
+        s_step = (time.perf_counter() - t1) / cpu_sweeps
+        cpu = {"kind": "extrapolated", "threads": threads, "sweeps_timed": cpu_sweeps, "oracle_s_per_step": s_step,
+               "node_updates_per_s": nint / s_step, "time_to_error_s": round(s_step * steps, 1),
+               "how": "the GPU's steps to the target times the oracle's OpenMP sweep time per step on the same "
+                      "operator"}
+        del op
     return {"workload": "cube8M: 3D 200^3 jittered grid (seed 2), m=4, n=70, dt=0.15*h^2/6", "mode": mode_name,
+            "cpu_time_to_error": cpu,
             "target_err_inf": target, "reached": bool(rep["err_met"]), "steps": steps, "wall_s": round(wall, 2),
             "device_s": round(dev_s, 2), "ms_per_step": 1e3 * dev_s / max(1, steps), "err_inf": rep["err_inf"],
             "err_mean_abs": rep["err_mean_abs"], "interior_nodes": nint, "setup_s": round(setup_s, 2),
