@@ -173,3 +173,17 @@ def test_nan_propagates_in_residual(p2):
     u[np.nonzero(p2["typ"] == 0)[0][10]] = np.nan
     _, r = op.sweep(p2["f"], p2["dt"], u)
     assert math.isnan(r)
+
+
+@pytest.mark.parametrize("which", ["p2", "p3"])
+@pytest.mark.parametrize("threads", [1, 4])
+def test_openmp_sweep_is_the_sequential_sweep(which, threads, request):
+    """The timed CPU baseline (row-parallel sweep) computes every row exactly
+    as the pinned sequential sweep: bitwise equal iterates and residual."""
+    p = request.getfixturevalue(which)
+    u = p["u0"] + 0.01 * np.cos(np.arange(len(p["u0"])))
+    u[p["typ"] == 1] = p["g"][p["typ"] == 1]
+    seq, res_seq = p["op"].sweep(p["f"], p["dt"], u)
+    par = np.empty_like(u)
+    res_par = p["op"].sweep_omp(p["f"], p["dt"], u, par, threads)
+    assert np.array_equal(seq, par) and res_seq == res_par
