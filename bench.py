@@ -392,8 +392,22 @@ def run_cube2m_adjoint(directions=32):
             errs.append(abs((grad * v).sum().item() - fd) / abs(fd))
             _progress(f"direction {j}: rel err {errs[-1]:.2e}")
             j += 1
+    # algorithmic bytes per step: forward 12n + 24 per interior row; a
+    # transposed step 12 B per entry of L_II (id and weight) plus lambda,
+    # lambda_new and the running sum read and written (32 B) per interior row
+    sten = p.get_stencils()[I]
+    valid = sten >= 0
+    nnz = int((valid & (typ_h[np.where(valid, sten, 0)] == 0)).sum())
+    del sten, valid
+    nint = int(I.sum())
+    fwd_bytes = (12 * wl.n + 24) * nint
+    adj_bytes = 12 * nnz + 32 * nint
+    fwd_ms, adj_ms = 1e3 * (t1 - t0) / K, 1e3 * (t2 - t1) / K
     return {"workload": "cube2M_adjoint: 3D 126^3 jittered grid (seed 4), m=4, n=70, K=2000, checkpoints every 100",
-            "interior_nodes": int(I.sum()), "forward_ckpt_s": round(t1 - t0, 3), "adjoint_s": round(t2 - t1, 3),
+            "interior_nodes": nint, "nnz_L_II": nnz, "forward_alg_GBps": round(fwd_bytes / fwd_ms / 1e6, 1),
+            "adjoint_alg_GBps": round(adj_bytes / adj_ms / 1e6, 1),
+            "adjoint_hbm_frac": round(adj_bytes / adj_ms / 1e6 / PEAK_HBM_GBS, 4),
+            "forward_ckpt_s": round(t1 - t0, 3), "adjoint_s": round(t2 - t1, 3),
             "first_forward_and_adjoint_s": round(first_s, 3),
             "adjoint_ms_per_step": round(1e3 * (t2 - t1) / K, 4), "forward_ms_per_step": round(1e3 * (t1 - t0) / K, 4),
             "J": loss.item(), "fd_eps": eps, "directions": directions, "max_rel_err_vs_fd": max(errs),
