@@ -271,32 +271,23 @@ hipError_t launch_pack_ell(hipStream_t s, int64_t row0, int64_t nrows, int32_t n
 }
 
 // Segment codes of one slice per workgroup (one wavefront): the distinct
-// aligned 4096-id blocks touched by the slice's entries of nonzero weight are
-// found in ascending order by repeated wavefront minima; with at most kSegs
-// of them the slice gets codes (cmode 1), else it keeps only its 32-bit ids
-// (cmode 0).  Entries of weight 0 (padding) contribute nothing to a row's sum
-// (the sum starts at +0 and the gathered values are finite), so they are not
-// gathered at all when a segment is left over: that segment's base lies past
-// the end of the gathered vector, whose buffer loads then return 0 without a
-// memory access.  Otherwise they are coded as column segbase[0].
-constexpr uint16_t kNoBlock = 0xffff;  // block of a zero-weight entry (ids < 0xffff * 4096)
+// aligned 4096-id blocks touched by any entry of the slice (padding entries
+// included, so every stored column stays encodable) are found in ascending
+// order by repeated wavefront minima; with at most kSegs of them the slice
+// gets codes (cmode 1), else it keeps only its 32-bit ids (cmode 0).
 __global__ __launch_bounds__(64) void k_encode_codes(const int64_t *__restrict__ slice_ptr,
                                                      const int32_t *__restrict__ slice_len,
                                                      const int32_t *__restrict__ idx, int64_t nslices,
                                                      const int64_t *__restrict__ cptr, uint16_t *__restrict__ code,
                                                      int32_t *__restrict__ segbase, int8_t *__restrict__ cmode,
-                                                     const double *__restrict__ w, float *__restrict__ w32q,
-                                                     int64_t ncols) {
+                                                     const double *__restrict__ w, float *__restrict__ w32q) {
     __shared__ uint16_t blk[kMaxSupport * kSlice];
     __shared__ int32_t list[kSegs];
     const int64_t s = blockIdx.x;
     const int lane = threadIdx.x;
     const int len = slice_len[s];
     const int64_t base = slice_ptr[s];
-    for (int k = 0; k < len; ++k) {
-        const int64_t p = ell_pos(1, base, k, lane);
-        blk[k * kSlice + lane] = w[p] != 0.0 ? (uint16_t)(idx[p] >> 12) : kNoBlock;
-    }
+    for (int k = 0; k < len; ++k) blk[k * kSlice + lane] = (uint16_t)(idx[ell_pos(1, base, k, lane)] >> 12);
     __syncthreads();
     int cnt = 0, cur = -1;
     bool over = false;
@@ -304,7 +295,7 @@ __global__ __launch_bounds__(64) void k_encode_codes(const int64_t *__restrict__
         int mn = 0x7fffffff;
         for (int k = 0; k < len; ++k) {
             const int v = blk[k * kSlice + lane];
-            if (v != kNoBlock && v > cur && v < mn) mn = v;
+            if (v > cur && v < mn) mn = v;
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -325,16 +316,13 @@ __global__ __launch_bounds__(64) void k_encode_codes(const int64_t *__restrict__
         if (lane == 0) cmode[s] = 0;
         return;
     }
-    // the first unused segment (if any) starts past the end of the vector
-    const int32_t past = (int32_t)((ncols + kSegSpan - 1) / kSegSpan) * kSegSpan;
-    if (lane < kSegs) segbase[s * kSegs + lane] = lane < cnt ? list[lane] << 12 : (lane == cnt || cnt == 0 ? past : list[0] << 12);
+    if (lane < kSegs) segbase[s * kSegs + lane] = (lane < cnt ? list[lane] : list[0]) << 12;
     if (lane == 0) cmode[s] = 1;
-    const uint16_t skip = cnt < kSegs ? (uint16_t)(cnt << 12) : 0;
     const int len4 = (len + 3) & ~3;
     uint16_t *out = code + cptr[s];
     for (int k = 0; k < len4; ++k) {
-        uint16_t c = skip;
-        if (k < len && blk[k * kSlice + lane] != kNoBlock) {
+        uint16_t c = 0;
+        if (k < len) {
             const int32_t col = idx[ell_pos(1, base, k, lane)];
             const int b = col >> 12;
             int seg = 0;
@@ -358,7 +346,7 @@ hipError_t launch_flag_near(hipStream_t s, int64_t N, int32_t n_max, const int32
 hipError_t launch_encode_codes(hipStream_t s, const Ell &e) {
     if (!e.nslices || e.layout != 1 || !e.code) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_encode_codes, dim3((unsigned)e.nslices), dim3(kSlice), 0, s, e.slice_ptr, e.slice_len, e.idx,
-                       e.nslices, e.cptr, e.code, e.segbase, e.cmode, e.w, e.w32q, e.ncols);
+                       e.nslices, e.cptr, e.code, e.segbase, e.cmode, e.w, e.w32q);
     return hipGetLastError();
 }
 

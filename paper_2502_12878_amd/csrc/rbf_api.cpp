@@ -577,7 +577,7 @@ rbf_status rbf_build_stencils(rbf_handle *h, int32_t n_uniform, const int16_t *n
 // must fit in 16 bits.  slen: the slice lengths.  RBF_ELL_CODES=0 skips them.
 static rbf_status attach_codes(rbf_handle *h, Ell &e, const std::vector<int32_t> &slen) {
     const char *cenv = std::getenv("RBF_ELL_CODES");
-    if (e.layout != 1 || !e.nslices || (cenv && cenv[0] == '0') || h->N >= ((int64_t)0xffff << 12)) return RBF_OK;
+    if (e.layout != 1 || !e.nslices || (cenv && cenv[0] == '0') || h->N >= ((int64_t)1 << 28)) return RBF_OK;
     std::vector<int64_t> cp((size_t)e.nslices + 1);
     cp[0] = 0;
     for (int64_t s = 0; s < e.nslices; ++s) cp[s + 1] = cp[s] + (int64_t)kSlice * ((slen[s] + 3) & ~3);
