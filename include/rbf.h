@@ -170,7 +170,7 @@ typedef struct {
 } rbf_iter_params;
 
 typedef struct {
-    int64_t steps;         /* explicit steps taken (mixed: outer passes*inner)      */
+    int64_t steps;         /* explicit steps taken (mixed: inner steps of all passes) */
     double res0;           /* max|L u0 - f| over interior nodes                     */
     double res_last;       /* residual seen at the last check                       */
     double res_final;      /* max|L u - f| of the returned iterate                  */
@@ -198,7 +198,10 @@ typedef struct {
  * target ends the run with RBF_OK.
  * Mixed mode: per outer pass r = f - L64 u (FP64 weights), then inner_steps
  * FP32 steps e <- e + dt (L32 e - (float)r) from e = 0 with FP32 weights and
- * accumulation, then u += e.  Requires keep_fp32 at rbf_compute_weights.
+ * accumulation, then u += e; the last pass runs fewer inner steps when
+ * max_steps is not a multiple of inner_steps.  Residual and error checks
+ * happen once per outer pass (`chunk` does not apply).  Requires keep_fp32
+ * at rbf_compute_weights.
  * Neumann nodes: f_dev on a Neumann node is its prescribed normal
  * derivative g_b.  Before every step each Neumann node takes
  * u_b = (g_b - sum_{k != b} w_bk u_k) / w_bb with the other support values of
@@ -238,13 +241,17 @@ rbf_status rbf_forward_ckpt(rbf_handle *h, const double *f_dev, const double *u0
 
 /* Gradient of J(u_K) with respect to f for K explicit steps: with
  * G = I + dt L_II and gK = dJ/du_K, grad = -dt sum_{j=0}^{K-1} (G^T)^j gK on
- * interior nodes, 0 on Dirichlet nodes.  The transposed steps run segment by
- * segment in reverse over the `every`-step checkpoint segments; ckpt_dev may
- * be NULL because this gradient does not depend on the states.  Each
- * transposed step is a gather sweep over L_II^T (built once, deterministic;
+ * interior nodes, 0 on Dirichlet nodes.  The sum is taken in Horner form,
+ * T_0 = 0, T_{j+1} = T_j + dt (L_II^T T_j + gK) = dt gK + G^T T_j, so that
+ * grad = -T_K: K forward sweeps over the transposed operator L_II^T (built
+ * once, each column's entries sorted by row, so results are deterministic;
  * the first call also encodes it and picks its launch shape, cached like the
- * shapes of rbf_autotune; RBF_TRANSPOSE_SCATTER=1 selects the atomic scatter
- * as for rbf_apply_transpose).  EINVAL when the node set has Neumann nodes. */
+ * shapes of rbf_autotune) with -gK in place of f, in graphs of `every` steps
+ * (one per checkpoint segment).  ckpt_dev may be NULL because this gradient
+ * does not depend on the states.  RBF_TRANSPOSE_SCATTER=1 instead forms the
+ * terms (G^T)^j gK one by one with the atomic scatter of
+ * rbf_apply_transpose and sums them.  EINVAL when the node set has Neumann
+ * nodes. */
 rbf_status rbf_adjoint_f(rbf_handle *h, const double *gK_dev, int64_t K, int64_t every,
                          const double *ckpt_dev, double *grad_f_dev, double dt);
 
@@ -287,7 +294,13 @@ rbf_status rbf_autotune(rbf_handle *h);
  * stored: column ids (4 B) or codes (2 B, plus the per-slice segment table)
  * and weights (8 B FP64 / 4 B FP32) of every slot including padding, slice
  * headers, and f, u and u_new of each interior row (8 B each in FP64; r, e
- * and e_new 4 B each in FP32).  The gathered values of u are not counted. */
+ * and e_new 4 B each in FP32).  The gathered values of u are not counted.
+ * Every 16-bit code is decoded back and compared with its 32-bit id when the
+ * codes are built; code_mismatches counts slices that failed (they are read
+ * through their 32-bit ids instead; 0 is expected).  The t_* fields describe
+ * the transposed interior operator L_II^T of the adjoint (all 0 until a
+ * transposed call has built it); its rows are the columns of L_II, so their
+ * length is a column's in-degree, which the support size does not bound. */
 typedef struct {
     int64_t n_interior, n_neumann;
     int64_t slices, slots;          /* slots: packed entries incl. padding */
@@ -298,7 +311,10 @@ typedef struct {
     double stream_bytes_f64, stream_bytes_f32;
     int32_t f64_temporal, f32_temporal;  /* code-reading sweeps: ordinary (1) or non-temporal (0) loads */
     int32_t f32_quad;                    /* FP32 weights of coded slices read in the code layout */
-    int32_t reserved;
+    int32_t code_mismatches;             /* slices whose codes failed the decode check */
+    int64_t t_slices, t_slots, t_coded_slices, t_code_mismatches;
+    int32_t t_max_len;                   /* longest transposed row (largest interior in-degree, even) */
+    int32_t t_waves, t_unroll, t_codes;  /* launch shape of the transposed sweep */
 } rbf_operator_info;
 
 /* Fill *info for the current operator (EINVAL without one). */

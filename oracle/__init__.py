@@ -34,12 +34,15 @@ class _IterReport(C.Structure):
 
 
 def lib():
-    """Load the oracle library, building it only if it is missing."""
+    """Load the oracle library, building it only if it is missing.  The
+    environment variable RBF_ORACLE_LIB names another build of the same source
+    to load instead (the sanitizer build of ``oracle.sanitize``)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = os.environ.get("RBF_ORACLE_LIB") or _build.LIB
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         L.orc_monomials.argtypes = [C.c_int, C.c_int, C.c_void_p]
         L.orc_monomials.restype = C.c_int
         L.orc_knn.argtypes = [C.c_int, C.c_int64, _f64p, C.c_int, _i64p, C.c_int64, _i32p]

@@ -53,7 +53,9 @@ class rbf_operator_info(C.Structure):
                 ("f32_pipeline", C.c_int32), ("f32_zigzag", C.c_int32), ("f32_codes", C.c_int32),
                 ("stream_bytes_f64", C.c_double), ("stream_bytes_f32", C.c_double),
                 ("f64_temporal", C.c_int32), ("f32_temporal", C.c_int32), ("f32_quad", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("code_mismatches", C.c_int32), ("t_slices", C.c_int64), ("t_slots", C.c_int64),
+                ("t_coded_slices", C.c_int64), ("t_code_mismatches", C.c_int64), ("t_max_len", C.c_int32),
+                ("t_waves", C.c_int32), ("t_unroll", C.c_int32), ("t_codes", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -274,7 +274,11 @@ hipError_t launch_pack_ell(hipStream_t s, int64_t row0, int64_t nrows, int32_t n
 // aligned 4096-id blocks touched by any entry of the slice (padding entries
 // included, so every stored column stays encodable) are found in ascending
 // order by repeated wavefront minima; with at most kSegs of them the slice
-// gets codes (cmode 1), else it keeps only its 32-bit ids (cmode 0).
+// gets codes (cmode 1), else it keeps only its 32-bit ids (cmode 0).  The
+// block numbers of a slice are staged in LDS when its rows hold at most
+// kMaxSupport entries (every forward operator); longer slices (rows of the
+// transposed operator, whose length is a column's in-degree and has no such
+// bound) read them from the id stream on every pass.
 __global__ __launch_bounds__(64) void k_encode_codes(const int64_t *__restrict__ slice_ptr,
                                                      const int32_t *__restrict__ slice_len,
                                                      const int32_t *__restrict__ idx, int64_t nslices,
@@ -287,14 +291,16 @@ __global__ __launch_bounds__(64) void k_encode_codes(const int64_t *__restrict__
     const int lane = threadIdx.x;
     const int len = slice_len[s];
     const int64_t base = slice_ptr[s];
-    for (int k = 0; k < len; ++k) blk[k * kSlice + lane] = (uint16_t)(idx[ell_pos(1, base, k, lane)] >> 12);
+    const bool staged = len <= kMaxSupport;
+    if (staged)
+        for (int k = 0; k < len; ++k) blk[k * kSlice + lane] = (uint16_t)(idx[ell_pos(1, base, k, lane)] >> 12);
     __syncthreads();
     int cnt = 0, cur = -1;
     bool over = false;
     for (int it = 0; it <= kSegs; ++it) {
         int mn = 0x7fffffff;
         for (int k = 0; k < len; ++k) {
-            const int v = blk[k * kSlice + lane];
+            const int v = staged ? (int)blk[k * kSlice + lane] : (int)(idx[ell_pos(1, base, k, lane)] >> 12);
             if (v > cur && v < mn) mn = v;
         }
 #pragma unroll
@@ -336,6 +342,36 @@ __global__ __launch_bounds__(64) void k_encode_codes(const int64_t *__restrict__
     }
 }
 
+// Every coded slot decoded back to its column and compared with the 32-bit
+// id it stands for; a slice with any difference loses its codes (cmode 0:
+// the sweeps read its 32-bit ids) and is counted in *bad.  One wavefront per
+// slice.
+__global__ __launch_bounds__(256) void k_check_codes(const int64_t *__restrict__ slice_ptr,
+                                                     const int32_t *__restrict__ slice_len,
+                                                     const int32_t *__restrict__ idx, int64_t nslices,
+                                                     const int64_t *__restrict__ cptr,
+                                                     const uint16_t *__restrict__ code,
+                                                     const int32_t *__restrict__ segbase, int8_t *__restrict__ cmode,
+                                                     unsigned long long *bad) {
+    const int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (s >= nslices || !cmode[s]) return;
+    const int len = slice_len[s];
+    const int64_t base = slice_ptr[s];
+    const uint16_t *in = code + cptr[s];
+    bool ok = true;
+    for (int k = 0; k < len; ++k) {
+        const uint32_t c = in[(int64_t)(k >> 2) * (4 * kSlice) + 4 * lane + (k & 3)];
+        const int32_t col = segbase[s * kSegs + (c >> 12)] + (int32_t)(c & (kSegSpan - 1));
+        ok = ok && col == idx[ell_pos(1, base, k, lane)];
+    }
+    if (__all(ok)) return;
+    if (lane == 0) {
+        cmode[s] = 0;
+        atomicAdd(bad, 1ull);
+    }
+}
+
 hipError_t launch_flag_near(hipStream_t s, int64_t N, int32_t n_max, const int32_t *sten, const int16_t *nrow,
                             const int8_t *type, int8_t *near) {
     if (N <= 0) return hipSuccess;
@@ -347,6 +383,13 @@ hipError_t launch_encode_codes(hipStream_t s, const Ell &e) {
     if (!e.nslices || e.layout != 1 || !e.code) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_encode_codes, dim3((unsigned)e.nslices), dim3(kSlice), 0, s, e.slice_ptr, e.slice_len, e.idx,
                        e.nslices, e.cptr, e.code, e.segbase, e.cmode, e.w, e.w32q);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_codes(hipStream_t s, const Ell &e, unsigned long long *bad) {
+    if (!e.nslices || e.layout != 1 || !e.code) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_check_codes, dim3(grid1d(e.nslices, 4)), dim3(256), 0, s, e.slice_ptr, e.slice_len, e.idx,
+                       e.nslices, e.cptr, e.code, e.segbase, e.cmode, bad);
     return hipGetLastError();
 }
 

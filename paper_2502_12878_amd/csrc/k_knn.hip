@@ -55,6 +55,13 @@ __global__ __launch_bounds__(256) void k_bbox(int dim, int64_t N, const double *
         }
 }
 
+// Candidate capacity exceeded at query q: the status records EOVERFLOW and
+// the lowest such node id (deterministic whatever order workgroups run in).
+__device__ void report_overflow(DevStatus *st, int64_t q) {
+    atomicCAS(&st->code, 0, (int)RBF_EOVERFLOW);
+    atomicMin((unsigned long long *)&st->info, (unsigned long long)q);
+}
+
 __device__ __forceinline__ int cell_coord(double x, double lo, double edge, int nc) {
     double t = (x - lo) / edge;
     int c = (int)t;
@@ -252,10 +259,7 @@ __global__ __launch_bounds__(64) void k_knn(CellGrid g, int64_t N, const double 
         const int nz = dim > 2 ? hi_c[2] - lo_c[2] + 1 : 1;
         const int nrows = ny * nz;
         if (nrows > kMaxRows || r > kMaxRing) {
-            if (lane == 0) {
-                atomicCAS(&status->code, 0, (int)RBF_EOVERFLOW);
-                status->info = q;
-            }
+            if (lane == 0) report_overflow(status, q);
             return;
         }
         for (int t = lane; t < nrows; t += 64) {
@@ -300,10 +304,7 @@ __global__ __launch_bounds__(64) void k_knn(CellGrid g, int64_t N, const double 
         count = s_count;
         __syncthreads();
         if (count > kCap) {
-            if (lane == 0) {
-                atomicCAS(&status->code, 0, (int)RBF_EOVERFLOW);
-                status->info = q;
-            }
+            if (lane == 0) report_overflow(status, q);
             return;
         }
         if (count >= n) break;

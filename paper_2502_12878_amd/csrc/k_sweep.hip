@@ -1,8 +1,8 @@
 // Sweep kernels of the explicit RBF-FD iteration (Sec. II-C, the Jacobi step
 // u <- u + dt (L_h u - f) with L_h u at a node a weighted sum over its support,
-// Sec. II), the single-operator kernels built from the same row sums, and the
-// adjoint's transposed gather.  All of them read a packed operator (sliced
-// ELL, 64 rows per slice = one wavefront; layouts and row sums in row_dot.h).
+// Sec. II) and the single-operator kernels built from the same row sums.  All
+// of them read a packed operator (sliced ELL, 64 rows per slice = one
+// wavefront; layouts and row sums in row_dot.h).
 //
 // The sweep is bound by HBM bandwidth: per interior node-update it moves the
 // row's column ids (4 B each, or 2 B as segment codes), its weights (8 B) and
@@ -18,6 +18,9 @@
 // contiguous window of the gathered vector instead of eight.  The shape
 // (workgroup size, unroll, layout, order) is chosen per operator by the
 // autotuner; every shape sums each row in the same order.
+//
+// The adjoint's transposed steps are this same sweep on the transposed
+// operator L_II^T (Horner form of the gradient sum; rbf_api.cpp).
 #include "row_dot.h"
 
 namespace rbf {
@@ -114,28 +117,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_outer_residual(
     if (res_slot) block_max_to_slot<WAVES>(bits, res_slot);
 }
 
-// One adjoint step on the transposed operator (rows of L^T = interior columns
-// of L): lam_new = lam + dt (L_II^T lam), acc += lam_new.
-template <int WAVES, int U, int LAYOUT>
-__global__ __launch_bounds__(WAVES * 64) void k_adjoint_gather(
-    const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
-    const double *__restrict__ w, Codes cs, int64_t nslices, int64_t N_int, int64_t ncols,
-    const double *__restrict__ lam_old, double *__restrict__ lam_new, double *__restrict__ acc, double dt, int order) {
-    const int64_t slice = slice_index<WAVES>(nslices, order);
-    const int lane = threadIdx.x & 63;
-    if (slice >= nslices) return;
-    const int len = slice_len[slice];
-    const double s =
-        row_dot<double, U, LAYOUT>(cs, slice_ptr, idx, w, BufGather<double>(lam_old, ncols), slice, lane, len);
-    const int64_t row = slice * kSlice + lane;
-    if (row < N_int) {
-        const double l = lam_old[row] + dt * s;
-        lam_new[row] = l;
-        acc[row] += l;
-    }
-}
-
-
 // Dispatch over the tuned (waves per block, unroll, layout) triples.
 template <template <int, int, int> class F, typename... A>
 hipError_t dispatch_shape(const SweepCfg &c, int layout, A &&...a) {
@@ -212,18 +193,6 @@ struct ApplyF64 {
 };
 
 template <int WV, int UN, int LY>
-struct AdjGather {
-    static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const double *lo, double *ln, double *acc,
-                          double dt, int remap) {
-        if (!e.nslices) return hipSuccess;
-        hipLaunchKernelGGL((k_adjoint_gather<WV, UN, LY>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
-                           e.slice_ptr, e.slice_len, e.idx, e.w, codes_of(e), e.nslices, N_int, e.ncols, lo, ln, acc,
-                           dt, remap);
-        return hipGetLastError();
-    }
-};
-
-template <int WV, int UN, int LY>
 struct OuterRes {
     static hipError_t run(hipStream_t s, const Ell &e, int64_t N_int, const double *f, const double *u, float *r32,
                           float *e0, unsigned long long *slot, int remap) {
@@ -265,13 +234,6 @@ hipError_t launch_apply_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int6
 hipError_t launch_outer_residual(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
                                  const double *u, float *r32, float *e0, unsigned long long *res_slot) {
     return dispatch_shape<OuterRes>(c, e.layout, s, e, N_int, f, u, r32, e0, res_slot, c.xcd_remap);
-}
-
-hipError_t launch_adjoint_gather(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *lam_old,
-                                 double *lam_new, double *acc, double dt, int parity) {
-    if (use_codes(c, e))
-        return dispatch_codes<AdjGather>(c, s, e, N_int, lam_old, lam_new, acc, dt, order_flags(c, parity));
-    return dispatch_shape<AdjGather>(c, e.layout, s, e, N_int, lam_old, lam_new, acc, dt, order_flags(c, parity));
 }
 
 }  // namespace rbf

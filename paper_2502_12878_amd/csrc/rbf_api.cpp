@@ -589,9 +589,16 @@ static rbf_status attach_codes(rbf_handle *h, Ell &e, const std::vector<int32_t>
     if (e.w32) ALLOC(h, e.w32q, float, e.celems);
     HIPCHK(h, hipMemcpyAsync(e.cptr, cp.data(), sizeof(int64_t) * (e.nslices + 1), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, launch_encode_codes(h->stream, e));
+    // every code decoded back and compared with its 32-bit id; a slice that
+    // fails keeps reading its ids
+    HIPCHK(h, launch_fill_u64(h->stream, 1, 0ull, h->dslots + 4));
+    HIPCHK(h, launch_check_codes(h->stream, e, h->dslots + 4));
+    HIPCHK(h, hipMemcpyAsync(h->hslots + 4, h->dslots + 4, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             h->stream));
     std::vector<int8_t> cm((size_t)e.nslices);
     HIPCHK(h, hipMemcpyAsync(cm.data(), e.cmode, (size_t)e.nslices, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    e.code_mismatches = (int64_t)h->hslots[4];
     e.coded_slices = 0;
     for (int8_t c : cm) e.coded_slices += c;
     return RBF_OK;
@@ -1181,10 +1188,12 @@ extern "C" rbf_status rbf_residual(rbf_handle *h, const double *f_dev, const dou
 }
 
 // ====================================================================== graphs
-enum GraphKind { kGraphF64 = 0, kGraphMixed = 1, kGraphAdjoint = 2, kGraphF64Quiet = 3, kGraphAdjointGather = 4 };
+enum GraphKind { kGraphF64 = 0, kGraphMixed = 1, kGraphAdjoint = 2, kGraphF64Quiet = 3, kGraphAdjointHorner = 4 };
 
 // FP64 chunk: reset the residual slot, `steps` sweeps alternating ua/ub
-// (starting from ua when start == 0), the last one reporting max |rho|.
+// (starting from ua when start == 0), the last one reporting max |rho|; with
+// inner == 1 (the first chunk of a run) the first sweep also reports its
+// max |rho|, the residual of the starting iterate, into slot 5.
 static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, double dt, int inner,
                             hipGraphExec_t *out) {
     const auto key = std::make_tuple(kind, steps, start + 2 * inner, double_bits(dt));
@@ -1198,7 +1207,9 @@ static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, d
     HIPCHK(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     if (kind == kGraphF64 || kind == kGraphF64Quiet) {
+        const bool first = kind == kGraphF64 && inner == 1;
         if (kind == kGraphF64) e = launch_fill_u64(s, 1, 0ull, h->dslots);
+        if (first && e == hipSuccess) e = launch_fill_u64(s, 1, 0ull, h->dslots + 5);
         double *a = start ? h->ub : h->ua, *b = start ? h->ua : h->ub;
         // With Neumann nodes updated in place, a step forks: the far interior
         // slices (whose rows read no Neumann value) are swept on a second
@@ -1207,7 +1218,7 @@ static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, d
         const bool fork = h->N_neu > 0 && h->neu_direct && h->far_slices > 0 && overlap_neumann();
         for (int64_t i = 0; i < steps && e == hipSuccess; ++i) {
             const bool report = kind == kGraphF64 && i == steps - 1;
-            unsigned long long *slot = report ? h->dslots : nullptr;
+            unsigned long long *slot = report ? h->dslots : (first && i == 0 ? h->dslots + 5 : nullptr);
             const int par = (int)(i & 1);
             if (fork) {
                 // the small Neumann launch is queued first so its workgroups
@@ -1253,12 +1264,13 @@ static rbf_status get_graph(rbf_handle *h, int kind, int64_t steps, int start, d
             e = launch_transpose_scatter(s, h->ell, Ni, h->ua, h->tmp);
             if (e == hipSuccess) e = launch_adjoint_update(s, Ni, dt, h->ua, h->ub, h->tmp);
         }
-    } else if (kind == kGraphAdjointGather) {
-        // `steps` transposed steps by gathering on L^T: lam alternates between
-        // ua and ub (from `start`), acc = tmp accumulates every new lam.
+    } else if (kind == kGraphAdjointHorner) {
+        // `steps` transposed steps in Horner form, T <- T + dt (L_II^T T + gK):
+        // the forward sweep on the transposed operator with tmp = -gK as its
+        // source; T alternates between ua and ub (from `start`).
         double *a = start ? h->ub : h->ua, *b = start ? h->ua : h->ub;
         for (int64_t i = 0; i < steps && e == hipSuccess; ++i) {
-            e = launch_adjoint_gather(s, h->cfgT, h->ellT, Ni, a, b, h->tmp, dt, (int)(i & 1));
+            e = launch_sweep_f64(s, h->cfgT, h->ellT, Ni, h->tmp, a, b, dt, nullptr, (int)(i & 1));
             std::swap(a, b);
         }
     }
@@ -1300,23 +1312,18 @@ extern "C" rbf_status rbf_iterate(rbf_handle *h, const double *f_dev, double *u_
     const int64_t N = h->N, Ni = h->N_int;
     const bool use_ref = p->u_ref_dev != nullptr;
     const bool err_stop = use_ref && p->err_target > 0.0;
+    const bool mixed = p->mode == RBF_MODE_MIXED;
 
     HIPCHK(h, launch_gather(h->stream, N, h->perm, u_dev, h->ua));
     HIPCHK(h, hipMemcpyAsync(h->ub, h->ua, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, launch_gather(h->stream, N, h->perm, f_dev, h->fint));
     if (use_ref) HIPCHK(h, launch_gather(h->stream, N, h->perm, p->u_ref_dev, h->uref));
-    // max |f| over interior rows (tmp = 0 as the reference)
+    // max |f| over interior rows (tmp = 0 as the reference), read back with
+    // the first chunk's report
     HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->tmp));
     HIPCHK(h, launch_fill_u64(h->stream, 2, 0ull, h->dslots));
     if (Ni) HIPCHK(h, launch_err_norm(h->stream, Ni, h->fint, h->tmp, h->part, kErrBlocks, h->dslots + 1));
-    HIPCHK(h, hipMemcpyAsync(h->hslots + 1, h->dslots + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    rep->fnorm = bits_to_double(h->hslots[1]);
-    double res0 = 0.0;
-    rbf_status st = residual_internal(h, h->ua, &res0);
-    if (st) return st;
-    rep->res0 = res0;
-    rep->res_last = res0;
+    HIPCHK(h, hipMemcpyAsync(h->hslots + 6, h->dslots + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
 
     auto finish_errors = [&](double *cur) -> rbf_status {
         if (!use_ref) return RBF_OK;
@@ -1329,18 +1336,34 @@ extern "C" rbf_status rbf_iterate(rbf_handle *h, const double *f_dev, double *u_
         rep->err_mean_abs = bits_to_double(h->hslots[2]) / (double)N;
         return RBF_OK;
     };
-
-    if (!std::isfinite(res0)) {
+    // a non-finite residual of u0 is divergence at step 0: u_dev keeps u0
+    auto diverged_at_start = [&](double res0) -> rbf_status {
         rep->diverged = 1;
         rep->diverged_step = 0;
-        rep->res_final = res0;
-        st = finish_errors(h->ua);
+        rep->steps = 0;
+        rep->res0 = rep->res_last = rep->res_final = res0;
+        HIPCHK(h, launch_gather(h->stream, N, h->perm, u_dev, h->ua));
+        rbf_status st = finish_errors(h->ua);
         if (st) return st;
         return fail(h, RBF_EDIVERGED, "non-finite initial residual (diverged at step 0)");
+    };
+
+    // The residual of u0 is the max |rho| of the first sweep (FP64 mode, no
+    // Neumann rows: the first chunk's graph reports it) or the first outer
+    // residual (mixed mode); otherwise, and when no step runs, it is
+    // evaluated here.
+    const bool fused_res0 = p->max_steps > 0 && (mixed || h->N_neu == 0);
+    double res0 = NAN;
+    if (!fused_res0) {
+        rbf_status st = residual_internal(h, h->ua, &res0);  // synchronises: fnorm is in hslots[6]
+        if (st) return st;
+        rep->res0 = res0;
+        rep->res_last = res0;
+        rep->fnorm = bits_to_double(h->hslots[6]);
+        if (!std::isfinite(res0)) return diverged_at_start(res0);
     }
 
     const bool tol_stop = p->tol_rel > 0.0;
-    const double tol_abs = p->tol_rel * rep->fnorm;
     double best = INFINITY;
     int64_t since_best = 0;
     int64_t steps = 0;
@@ -1348,115 +1371,92 @@ extern "C" rbf_status rbf_iterate(rbf_handle *h, const double *f_dev, double *u_
     double dev_ms = 0.0, sweep_ms = 0.0;
     int64_t sweeps_timed = 0;
     rbf_status status = (tol_stop || err_stop) ? RBF_ENOTCONVERGED : RBF_OK;
+    bool first = true;
 
-    if (p->mode == RBF_MODE_FP64) {
-        while (steps < p->max_steps) {
-            const int64_t s = std::min<int64_t>(p->chunk, p->max_steps - steps);
-            hipGraphExec_t ex;
-            st = get_graph(h, kGraphF64, s, cur, p->dt, 0, &ex);
-            if (st) return st;
-            HIPCHK(h, hipEventRecord(h->ev0, h->stream));
-            HIPCHK(h, hipGraphLaunch(ex, h->stream));
-            HIPCHK(h, hipEventRecord(h->ev1, h->stream));
-            if (s & 1) cur ^= 1;
+    while (steps < p->max_steps) {
+        // FP64: a chunk of sweeps; mixed: one outer pass (u stays in ua), the
+        // last one shortened so that max_steps is not exceeded
+        const int64_t s = mixed ? std::min<int64_t>(p->inner_steps, p->max_steps - steps)
+                                : std::min<int64_t>(p->chunk, p->max_steps - steps);
+        hipGraphExec_t ex;
+        rbf_status st = mixed ? get_graph(h, kGraphMixed, use_ref ? 1 : 0, 0, p->dt, (int)s, &ex)
+                              : get_graph(h, kGraphF64, s, cur, p->dt, (first && fused_res0) ? 1 : 0, &ex);
+        if (st) return st;
+        HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+        HIPCHK(h, hipGraphLaunch(ex, h->stream));
+        HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+        if (!mixed && (s & 1)) cur ^= 1;
+        int nslot = mixed ? 2 : 1;
+        if (!mixed && err_stop) {
             double *u_now = cur ? h->ub : h->ua;
-            int nslot = 1;
-            if (err_stop) {
-                HIPCHK(h, launch_fill_u64(h->stream, 1, 0ull, h->dslots + 1));
-                HIPCHK(h, launch_err_norm(h->stream, N, u_now, h->uref, h->part, kErrBlocks, h->dslots + 1));
-                nslot = 2;
-            }
-            HIPCHK(h, hipMemcpyAsync(h->hslots, h->dslots, nslot * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
-            HIPCHK(h, hipStreamSynchronize(h->stream));
-            float ms = 0.f;
-            HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
-            dev_ms += ms;
+            HIPCHK(h, launch_fill_u64(h->stream, 1, 0ull, h->dslots + 1));
+            HIPCHK(h, launch_err_norm(h->stream, N, u_now, h->uref, h->part, kErrBlocks, h->dslots + 1));
+            nslot = 2;
+        }
+        HIPCHK(h, hipMemcpyAsync(h->hslots, h->dslots, nslot * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+        if (first && fused_res0 && !mixed)
+            HIPCHK(h, hipMemcpyAsync(h->hslots + 5, h->dslots + 5, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                     h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        float ms = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        dev_ms += ms;
+        const double res = bits_to_double(h->hslots[0]);  // residual of the iterate entering the last step
+        if (first && fused_res0) {
+            // a chunk of one step (and every mixed pass) reports the residual
+            // of its starting iterate in slot 0
+            res0 = (mixed || s == 1) ? res : bits_to_double(h->hslots[5]);
+            rep->res0 = res0;
+            rep->fnorm = bits_to_double(h->hslots[6]);
+            if (!std::isfinite(res0)) return diverged_at_start(res0);
+        }
+        first = false;
+        if (!mixed) {
             sweep_ms += ms;
             sweeps_timed += s;
-            steps += s;
-            rep->checks++;
-            const double res = bits_to_double(h->hslots[0]);
-            rep->res_last = res;
-            if (!std::isfinite(res) || res > 1e6 * res0) {
-                rep->diverged = 1;
-                rep->diverged_step = steps;
-                status = RBF_EDIVERGED;
-                break;
-            }
-            if (err_stop && bits_to_double(h->hslots[1]) <= p->err_target) {
-                rep->err_met = 1;
-                rep->converged = 1;
-                status = RBF_OK;
-                break;
-            }
-            if (tol_stop && res <= tol_abs) {
-                rep->converged = 1;
-                status = RBF_OK;
-                break;
-            }
-            if (res < best) {
-                best = res;
-                since_best = 0;
-            } else if (p->stall_chunks > 0 && ++since_best >= p->stall_chunks) {
-                break;
-            }
         }
+        steps += s;
+        rep->checks++;
+        rep->res_last = res;
+        if (!std::isfinite(res) || res > 1e6 * res0) {
+            rep->diverged = 1;
+            rep->diverged_step = steps;
+            status = RBF_EDIVERGED;
+            break;
+        }
+        if (err_stop && bits_to_double(h->hslots[1]) <= p->err_target) {
+            rep->err_met = 1;
+            rep->converged = 1;
+            status = RBF_OK;
+            break;
+        }
+        if (tol_stop && res <= p->tol_rel * rep->fnorm) {
+            rep->converged = 1;
+            status = RBF_OK;
+            break;
+        }
+        if (res < best) {
+            best = res;
+            since_best = 0;
+        } else if (p->stall_chunks > 0 && ++since_best >= p->stall_chunks) {
+            break;
+        }
+    }
+    if (!mixed) {
         h->last_sweep_sec = sweeps_timed ? sweep_ms * 1e-3 / (double)sweeps_timed : 0.0;
         h->last_sweeps = sweeps_timed;
-    } else {
-        // mixed precision: one graph per outer pass (cur stays 0: u lives in ua)
-        const int inner = p->inner_steps;
-        while (steps < p->max_steps) {
-            hipGraphExec_t ex;
-            st = get_graph(h, kGraphMixed, use_ref ? 1 : 0, 0, p->dt, inner, &ex);
-            if (st) return st;
-            HIPCHK(h, hipEventRecord(h->ev0, h->stream));
-            HIPCHK(h, hipGraphLaunch(ex, h->stream));
-            HIPCHK(h, hipEventRecord(h->ev1, h->stream));
-            HIPCHK(h, hipMemcpyAsync(h->hslots, h->dslots, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
-            HIPCHK(h, hipStreamSynchronize(h->stream));
-            float ms = 0.f;
-            HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
-            dev_ms += ms;
-            steps += inner;
-            rep->checks++;
-            const double res = bits_to_double(h->hslots[0]);  // residual of u entering the pass
-            rep->res_last = res;
-            if (!std::isfinite(res) || res > 1e6 * res0) {
-                rep->diverged = 1;
-                rep->diverged_step = steps;
-                status = RBF_EDIVERGED;
-                break;
-            }
-            if (err_stop && bits_to_double(h->hslots[1]) <= p->err_target) {
-                rep->err_met = 1;
-                rep->converged = 1;
-                status = RBF_OK;
-                break;
-            }
-            if (tol_stop && res <= tol_abs) {
-                rep->converged = 1;
-                status = RBF_OK;
-                break;
-            }
-            if (res < best) {
-                best = res;
-                since_best = 0;
-            } else if (p->stall_chunks > 0 && ++since_best >= p->stall_chunks) {
-                break;
-            }
-        }
     }
     double *u_fin = cur ? h->ub : h->ua;
     rep->steps = steps;
     rep->seconds = dev_ms * 1e-3;
     HIPCHK(h, launch_scatter(h->stream, N, h->perm, u_fin, u_dev));
     double resf = 0.0;
-    st = residual_internal(h, u_fin, &resf);
+    rbf_status st = residual_internal(h, u_fin, &resf);
     if (st) return st;
     rep->res_final = resf;
     st = finish_errors(u_fin);
     if (st) return st;
+    const double tol_abs = p->tol_rel * rep->fnorm;
     if (status == RBF_EDIVERGED)
         return fail(h, status, "diverged: residual %g at step %" PRId64 " (initial %g)", rep->res_last, rep->diverged_step, res0);
     if (status == RBF_ENOTCONVERGED)
@@ -1518,6 +1518,18 @@ extern "C" rbf_status rbf_get_operator_info(const rbf_handle *h, rbf_operator_in
     info->f32_quad = info->f32_codes && b.quad && e.w32q ? 1 : 0;
     info->stream_bytes_f64 = stream_bytes(h, 8, 8, info->f64_codes, false);
     info->stream_bytes_f32 = h->have_w32 ? stream_bytes(h, 4, 4, info->f32_codes, info->f32_quad) : 0.0;
+    info->code_mismatches = (int32_t)e.code_mismatches;
+    const Ell &t = h->ellT;
+    if (t.idx) {
+        info->t_slices = t.nslices;
+        info->t_slots = t.elems;
+        info->t_coded_slices = t.cmode ? t.coded_slices : 0;
+        info->t_code_mismatches = t.code_mismatches;
+        info->t_max_len = t.max_len;
+        info->t_waves = h->cfgT.waves_per_block;
+        info->t_unroll = h->cfgT.unroll;
+        info->t_codes = h->cfgT.codes && t.cmode ? 1 : 0;
+    }
     return RBF_OK;
 }
 
@@ -1598,8 +1610,8 @@ static rbf_status tune_transpose(rbf_handle *h) {
                         c.codes = cd;
                         c.temporal = tp;
                         auto launch = [&](int r) {
-                            return launch_adjoint_gather(h->stream, c, e, Ni, (r & 1) ? h->ub : h->ua,
-                                                         (r & 1) ? h->ua : h->ub, h->tmp, 0.0, r & 1);
+                            return launch_sweep_f64(h->stream, c, e, Ni, h->tmp, (r & 1) ? h->ub : h->ua,
+                                                    (r & 1) ? h->ua : h->ub, 0.0, nullptr, r & 1);
                         };
                         HIPCHK(h, launch(0));
                         HIPCHK(h, hipEventRecord(h->ev0, h->stream));
@@ -1634,41 +1646,51 @@ extern "C" rbf_status rbf_adjoint_f(rbf_handle *h, const double *gK_dev, int64_t
     if (!std::isfinite(dt)) return fail(h, RBF_EINVAL, "dt must be finite");
     DeviceGuard g(h->device);
     const int64_t N = h->N, Ni = h->N_int;
-    const bool scatter = use_scatter_transpose();
-    if (!scatter) {
-        rbf_status st = build_transpose(h);
-        if (!st) st = tune_transpose(h);
-        if (st) return st;
-    }
-    // lam = gK on interior rows (0 elsewhere); acc = lam
-    HIPCHK(h, launch_gather(h->stream, N, h->perm, gK_dev, h->ua));
-    HIPCHK(h, launch_fill_f64(h->stream, N - Ni, 0.0, h->ua + Ni));
-    if (scatter) {  // acc in ub, scatter target tmp
+    const int64_t nseg = K / every;
+    if (use_scatter_transpose()) {
+        // lam = gK on interior rows (0 elsewhere) in ua, acc = lam in ub, the
+        // scatter target tmp = 0; K-1 scattered steps lam <- G^T lam, acc += lam
+        HIPCHK(h, launch_gather(h->stream, N, h->perm, gK_dev, h->ua));
+        HIPCHK(h, launch_fill_f64(h->stream, N - Ni, 0.0, h->ua + Ni));
         HIPCHK(h, hipMemcpyAsync(h->ub, h->ua, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
         HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->tmp));
-    } else {  // lam alternates ua/ub, acc in tmp
-        HIPCHK(h, hipMemcpyAsync(h->tmp, h->ua, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
-        HIPCHK(h, launch_fill_f64(h->stream, N - Ni, 0.0, h->ub + Ni));
+        for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+            const int64_t steps = seg == 0 ? every - 1 : every;
+            if (steps <= 0) continue;
+            hipGraphExec_t ex;
+            rbf_status st = get_graph(h, kGraphAdjoint, steps, 0, dt, 0, &ex);
+            if (st) return st;
+            HIPCHK(h, hipGraphLaunch(ex, h->stream));
+        }
+        HIPCHK(h, launch_scale_interior(h->stream, N, Ni, -dt, h->ub, h->tmp));
+        HIPCHK(h, launch_scatter(h->stream, N, h->perm, h->tmp, grad_f_dev));
+        HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->tmp));
+        return RBF_OK;
     }
-    // K-1 transposed steps, segment by segment from the last checkpoint
-    // interval back to the first; the first interval has one step fewer.
-    const int64_t nseg = K / every;
+    rbf_status st = build_transpose(h);
+    if (!st) st = tune_transpose(h);
+    if (st) return st;
+    // Horner form of grad = -dt sum_{j<K} (G^T)^j gK: with T_0 = 0 and
+    // T_{j+1} = T_j + dt (L_II^T T_j + gK) = dt gK + G^T T_j, T_K = dt times
+    // the sum, so grad = -T_K.  Each step is the forward sweep on L_II^T with
+    // source -gK (in tmp); T lives in ua / ub, 0 on Dirichlet nodes.
+    HIPCHK(h, launch_gather(h->stream, N, h->perm, gK_dev, h->ua));
+    HIPCHK(h, launch_scale_interior(h->stream, N, Ni, -1.0, h->ua, h->tmp));
+    HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->ua));
+    HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->ub));
+    // K steps in graphs of `every` (one per checkpoint segment, run from the
+    // last segment back to the first)
     int cur = 0;
     for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-        const int64_t steps = seg == 0 ? every - 1 : every;
-        if (steps <= 0) continue;
         hipGraphExec_t ex;
-        rbf_status st = get_graph(h, scatter ? kGraphAdjoint : kGraphAdjointGather, steps, scatter ? 0 : cur, dt, 0, &ex);
+        st = get_graph(h, kGraphAdjointHorner, every, cur, dt, 0, &ex);
         if (st) return st;
         HIPCHK(h, hipGraphLaunch(ex, h->stream));
-        if (!scatter && (steps & 1)) cur ^= 1;
+        if (every & 1) cur ^= 1;
     }
-    double *acc = scatter ? h->ub : h->tmp;
-    double *out = scatter ? h->tmp : h->ub;
-    HIPCHK(h, launch_scale_interior(h->stream, N, Ni, -dt, acc, out));
+    double *T = cur ? h->ub : h->ua, *out = cur ? h->ua : h->ub;
+    HIPCHK(h, launch_scale_interior(h->stream, N, Ni, -1.0, T, out));
     HIPCHK(h, launch_scatter(h->stream, N, h->perm, out, grad_f_dev));
-    // leave tmp zeroed for the next scattered transpose
-    HIPCHK(h, launch_fill_f64(h->stream, N, 0.0, h->tmp));
     return RBF_OK;
 }
 

@@ -74,6 +74,7 @@ struct Ell {
     float *w32q = nullptr;         // [celems] FP32 weights of coded slices in the code layout, or null
     int64_t celems = 0;
     int64_t coded_slices = 0;      // slices with cmode 1
+    int64_t code_mismatches = 0;   // slices whose codes failed the decode check (kept on 32-bit ids)
 };
 
 constexpr int kSegs = 16;
@@ -132,7 +133,7 @@ struct rbf_handle {
 
     rbf::SweepCfg cfg;    // FP64 sweep family
     rbf::SweepCfg cfg32;  // FP32 inner sweeps
-    rbf::SweepCfg cfgT;   // transposed gather of the adjoint
+    rbf::SweepCfg cfgT;   // sweep on the transposed operator (adjoint)
     bool tunedT = false;
     int weights_panel = 16;
     double last_sweep_sec = 0.0;
@@ -198,6 +199,7 @@ hipError_t launch_pack_ell(hipStream_t s, int64_t row0, int64_t nrows, int32_t n
                            const int32_t *iperm, const int32_t *sten, const int16_t *nrow, const double *w_can,
                            const Ell &e, double *wself, int32_t *foreign);
 hipError_t launch_encode_codes(hipStream_t s, const Ell &e);
+hipError_t launch_check_codes(hipStream_t s, const Ell &e, unsigned long long *bad);
 hipError_t launch_flag_near(hipStream_t s, int64_t N, int32_t n_max, const int32_t *sten, const int16_t *nrow,
                             const int8_t *type, int8_t *near);
 hipError_t launch_neumann_update(hipStream_t s, const Ell &e, int64_t N_int, int64_t N_neu, const double *wself,
@@ -218,8 +220,6 @@ hipError_t launch_apply_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int6
 hipError_t launch_outer_residual(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *f,
                                  const double *u, float *r32, float *e0, unsigned long long *res_slot);
 hipError_t launch_add_correction(hipStream_t s, int64_t N_int, double *u, const float *e);
-hipError_t launch_adjoint_gather(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const double *lam_old,
-                                 double *lam_new, double *acc, double dt, int parity);
 hipError_t launch_tcount(hipStream_t s, int64_t N, int32_t n_max, int64_t N_int, const int8_t *type,
                          const int32_t *iperm, const int32_t *sten, const int16_t *nrow, int32_t *cnt);
 hipError_t launch_tfill(hipStream_t s, int64_t N, int32_t n_max, int64_t N_int, const int8_t *type,

@@ -112,3 +112,30 @@ def test_adjoint_matches_central_differences():
         v /= np.abs(v).max()
         fd = (J(f + eps * v) - J(f - eps * v)) / (2 * eps)
         assert abs(np.dot(grad, v) - fd) <= 1e-6 * abs(fd)
+
+
+def test_transposed_rows_outgrow_the_support_size():
+    """A row of L_II^T lists the interior rows whose supports hold a given
+    interior node, so its length is that node's in-degree.  In-degrees are not
+    bounded by n: in a 16^3 cube at n = 256 some exceed 300 (nodes near the
+    centre sit in the supports of boundary-near rows, which reach inwards).
+    The oracle's transposed product agrees with the dense transpose there."""
+    xyz, typ = ri.jittered_grid(3, 16, 0.3, 41)
+    idx = oracle.knn(xyz, 256)
+    I = typ == 0
+    cols = idx[I].reshape(-1)
+    cols = cols[I[cols]]
+    deg = np.bincount(cols, minlength=len(typ))[I]
+    assert deg.max() > 256 and deg.sum() == cols.size
+    # transposed product with arbitrary weights against the dense matrix
+    rng = np.random.default_rng(3)
+    w = np.where(I[:, None], rng.standard_normal(idx.shape), 0.0)
+    op = oracle.Operator(typ, idx, w)
+    L = np.zeros((len(typ), len(typ)))
+    rows = np.repeat(np.arange(len(typ)), idx.shape[1])
+    np.add.at(L, (rows, idx.reshape(-1)), w.reshape(-1))
+    Lii = L[np.ix_(I, I)]
+    v = rng.standard_normal(len(typ))
+    t = op.apply_transpose(v)
+    assert np.abs(t[I] - Lii.T @ v[I]).max() <= 1e-12 * np.abs(Lii.T @ v[I]).max()
+    assert (t[~I] == 0).all()

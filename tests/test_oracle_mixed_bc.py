@@ -165,3 +165,26 @@ def test_apply_gives_normal_derivative_of_linear_fields():
     assert np.abs(Lu[B] - a @ normals[:, B]).max() <= 1e-10
     assert np.abs(Lu[typ == 0]).max() <= 1e-8
     assert (Lu[typ == 1] == 0).all()
+
+
+@pytest.mark.parametrize("dim,side,n", [(2, 15, 12), (3, 9, 70)])
+def test_neumann_supports_hold_interior_nodes_only(dim, side, n):
+    """A Neumann node's support is the node itself and its nearest interior
+    nodes (its value is set from interior values, Sec. II-C): the oracle's
+    typed search against a numpy brute force over {itself} and the interior
+    nodes, with the same key (d2, id), d2 = (dx*dx + dy*dy) + dz*dz."""
+    xyz, typ, _ = ri.mixed_bc_grid(dim, side, 0.3, 17)
+    idx = oracle.knn(xyz, n, typ=typ)
+    interior = np.nonzero(typ == 0)[0]
+    for c in np.nonzero(typ == 2)[0]:
+        cand = np.concatenate([[c], interior])
+        d = [xyz[a, cand] - xyz[a, c] for a in range(dim)]
+        d2 = d[0] * d[0]
+        for a in range(1, dim):
+            d2 = d2 + d[a] * d[a]
+        order = np.lexsort((cand, d2))
+        assert np.array_equal(idx[c], cand[order[:n]])
+        assert idx[c, 0] == c and (typ[idx[c, 1:]] == 0).all()
+    # the other rows are the plain search
+    other = np.nonzero(typ != 2)[0]
+    assert np.array_equal(idx[other], oracle.knn(xyz, n, rows=other))
