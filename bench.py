@@ -9,8 +9,12 @@ and max-residual reduction), run by the library in HIP-graph chunks.
 
 Prints one JSON line: node-updates/s (value), HBM GB/s of the sweep kernel
 against the 8 TB/s peak (roofline), setup times, time to L-inf error 1e-6
-for FP64 vs FP32+FP64 refinement, and the CPU oracle's OpenMP sweep as a
-baseline.  Inputs are synthetic and seeded; they are in HBM before timing.
+for FP64 vs FP32+FP64 refinement on the 1M-node cube, the CPU oracle's
+OpenMP sweep on the same operator as a baseline, the 8M-node cube's FP32 +
+refinement vs FP64 step times (2,000 steps each), and the 2M-node adjoint
+gradient against central differences on 32 directions and against the
+oracle's transposed loop.  Inputs are synthetic and seeded; they are in HBM
+before timing.
 """
 import argparse
 import hashlib
@@ -80,11 +84,23 @@ def setup_problem(m, keep_fp32=False, autotune=True):
 
 
 def time_sweeps(s, steps, warmup, chunk=500):
+    """Wall time of one call of `steps` explicit steps in graph chunks of
+    min(chunk, steps), after untimed warm-up calls identical to it (so its
+    graphs are built and cached before timing) covering at least `warmup`
+    steps; also the device time per sweep (events around the chunk graphs)
+    of the timed call.  Returns (wall s, s per sweep, sweeps timed, report,
+    warm-up steps run)."""
     import torch
     p, wl = s["p"], s["wl"]
-    u = s["u0"].clone()
-    st, _ = p.iterate(s["f"], u, wl.dt, warmup, 0.0, min(chunk, max(1, warmup)))
-    assert st == 0, st
+    chunk = max(1, min(chunk, steps))
+    warm = 0
+    while True:
+        u = s["u0"].clone()
+        st, _ = p.iterate(s["f"], u, wl.dt, steps, 0.0, chunk)
+        assert st == 0, st
+        warm += steps
+        if warm >= warmup:
+            break
     u = s["u0"].clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -93,7 +109,7 @@ def time_sweeps(s, steps, warmup, chunk=500):
     t1 = time.perf_counter()
     assert st == 0, (st, rep)
     per_sweep, nsw = p.last_sweep_time()
-    return t1 - t0, per_sweep, nsw, rep
+    return t1 - t0, per_sweep, nsw, rep, warm
 
 
 def time_to_error(s, target, inner=500, max_steps=2_000_000):
@@ -153,41 +169,130 @@ def run_cube1m_fp32(steps=2000, warmup=500, inner=500):
     return out
 
 
-def cpu_baseline(budget_s=10.0):
-    """The oracle's OpenMP sweep on a bounded sample of the workload: the same
-    generator and parameters (3D, jitter 0.3h, seed 1, m = 4, n = 70) on a
-    30^3 grid, whose supports and weights the oracle itself can build in
-    seconds; timed for ~budget_s after an untimed setup."""
+def _time_oracle_sweeps(op, f, u0, dt, threads, budget_s, min_sweeps):
+    """Node-update rate of the oracle's OpenMP sweep (row-parallel for) with
+    `threads` threads: at least `min_sweeps` sweeps and `budget_s` seconds,
+    after one untimed sweep."""
+    a, b = u0.copy(), u0.copy()
+    op.sweep_omp(f, dt, a, b, threads)
+    sweeps = 0
+    t0 = time.perf_counter()
+    while True:
+        op.sweep_omp(f, dt, a, b, threads)
+        a, b = b, a
+        sweeps += 1
+        el = time.perf_counter() - t0
+        if sweeps >= min_sweeps and el >= budget_s:
+            return sweeps, el
+
+
+def cpu_baseline(s, budget_s=8.0):
+    """The oracle's OpenMP sweep (the paper's intra-node row-parallel loop)
+    on the headline operator itself: the supports and weights of the 1M-node
+    cube exported from the library (rbf_get_stencils / rbf_get_weights),
+    timed with every host core the process may use and with one thread.  A
+    30^3 instance of the same workload, whose operator the oracle builds
+    itself, is timed beside it as a secondary figure."""
     import numpy as np
 
     import oracle
     import rbf_inputs as ri
-    side, m, n = 30, 4, 70
-    xyz, typ = ri.jittered_grid(3, side, 0.3, 1)
-    idx, w = oracle.setup(xyz, typ, n, m=m)
-    u_ex, f, g, u0 = ri.manufactured(3, xyz, typ)
-    h = ri.grid_spacing(side)
-    dt = 0.15 * h * h / 6
-    op = oracle.Operator(typ, idx, w)
     threads = len(os.sched_getaffinity(0))
-    a, b = u0.copy(), u0.copy()
+    p = s["p"]
+    typ = s["typ"]
     nint = int((typ == 0).sum())
-    res = {}
-    for nt in (threads, 1):
-        steps = 0
-        t0 = time.perf_counter()
-        while True:
-            op.sweep_omp(f, dt, a, b, nt)
-            a, b = b, a
-            steps += 1
-            el = time.perf_counter() - t0
-            if el >= (budget_s if nt == threads else budget_s / 4):
-                break
-        res[nt] = nint * steps / el
-    return {"value": res[threads], "unit": "node-updates/s", "cores": threads, "kind": "oracle",
-            "single_thread_value": res[1],
-            "sample": f"oracle OpenMP sweep (row-parallel for) on the same workload generator at 30^3 nodes "
-                      f"({nint} interior rows, m=4, n=70), {budget_s:.0f} s window after an untimed oracle setup"}
+    op = oracle.Operator(typ, p.get_stencils(), p.get_weights())
+    f, u0, dt = s["f_h"], s["u0_h"], s["wl"].dt
+    sw_all, el_all = _time_oracle_sweeps(op, f, u0, dt, threads, budget_s, 20)
+    sw_one, el_one = _time_oracle_sweeps(op, f, u0, dt, 1, budget_s / 2, 2)
+    del op
+    # secondary: 30^3 instance built by the oracle
+    side, m, n = 30, 4, 70
+    xyz3, typ3 = ri.jittered_grid(3, side, 0.3, 1)
+    idx3, w3 = oracle.setup(xyz3, typ3, n, m=m)
+    _, f3, _, u03 = ri.manufactured(3, xyz3, typ3)
+    op3 = oracle.Operator(typ3, idx3, w3)
+    nint3 = int((typ3 == 0).sum())
+    h3 = ri.grid_spacing(side)
+    sw3, el3 = _time_oracle_sweeps(op3, f3, u03, 0.15 * h3 * h3 / 6, threads, 2.0, 20)
+    return {"value": nint * sw_all / el_all, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": nint * sw_one / el_one,
+            "sweeps_timed": sw_all, "single_thread_sweeps_timed": sw_one,
+            "alg_GBps": round((12 * 70 + 24) * nint * sw_all / el_all / 1e9, 2),
+            "sample": f"oracle OpenMP sweep (row-parallel for) on the cube1M m=4 operator exported from the GPU "
+                      f"({nint} interior rows, n=70): {sw_all} sweeps on {threads} threads ({el_all:.1f} s) and "
+                      f"{sw_one} on 1 thread ({el_one:.1f} s), after one untimed sweep each",
+            "secondary_30cube": {"value": nint3 * sw3 / el3, "interior_nodes": nint3, "sweeps_timed": sw3,
+                                 "note": "same generator and parameters at 30^3 (operator built by the oracle; "
+                                         "~19 MB, partly cache-resident on the host)"}}
+
+
+def run_c2_block(steps=2000, warmup=1000, inner=500, target=1e-6, builder_steps_to_target=740_500):
+    """The 8M-node cube (200^3, seed 2, m = 4, n = 70): `steps` explicit steps
+    in each mode, plain FP64 sweeps and FP32 inner sweeps of `inner` steps
+    inside the FP64 residual correction, with the error against the exact
+    solution checked every 500 steps as in a time-to-error run; device and
+    wall time per step, their ratio, and both iterates compared.  Time to
+    L-inf error `target` is extrapolated from the step count the full runs
+    needed (measured by the builder, 740,500 steps in both modes)."""
+    import torch
+
+    import rbf_inputs as ri
+    from paper_2502_12878_amd import RBF_MODE_FP64, RBF_MODE_MIXED, Problem
+    wl = ri.workload("cube8M")
+    p = Problem(0)
+    t0 = time.perf_counter()
+    xd, td = p.build_nodes(wl.dim, wl.side, wl.jitter, wl.seed)
+    p.set_nodes(xd, td)
+    del xd, td
+    p.build_stencils(wl.n)
+    p.compute_weights(wl.m, keep_fp32=True)
+    p.autotune()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    xyz_h, typ_h = wl.nodes()
+    u_ex, f, g, u0 = ri.manufactured(wl.dim, xyz_h, typ_h)
+    nint = int((typ_h == 0).sum())
+    del xyz_h
+    fd, uref, u0d = _dev(f), _dev(u_ex), _dev(u0)
+    del u_ex, f, g
+    out = {"workload": f"cube8M: 3D 200^3 jittered grid (seed 2), m=4, n=70, dt=0.15*h^2/6, {steps} steps per mode "
+                       f"(error vs exact checked every 500 steps)", "interior_nodes": nint,
+           "setup_s": round(setup_s, 2)}
+    finals = {}
+    for name, mode in (("fp64", RBF_MODE_FP64), ("fp32_refine", RBF_MODE_MIXED)):
+        kw = dict(mode=mode, inner_steps=inner, u_ref=uref, err_target=target)
+        u = u0d.clone()
+        p.iterate(fd, u, wl.dt, warmup, 0.0, 500, **kw)  # builds the graphs the timed call uses
+        u = u0d.clone()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, rep = p.iterate(fd, u, wl.dt, steps, 0.0, 500, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        assert rep["steps"] == steps, rep
+        per = rep["seconds"] / steps
+        alg = (12 * wl.n + 24) if mode == RBF_MODE_FP64 else (8 * wl.n + 12)
+        out[name] = {"status": st, "steps": steps, "device_s": round(rep["seconds"], 4), "wall_s": round(wall, 4),
+                     "ms_per_step_device": round(1e3 * per, 5), "ms_per_step_wall": round(1e3 * wall / steps, 5),
+                     "alg_bytes_per_update": alg, "alg_GBps": round(alg * nint / per / 1e9, 1),
+                     "err_inf_vs_exact": rep["err_inf"],
+                     "time_to_error_extrapolated_s": round(per * builder_steps_to_target, 1)}
+        finals[name] = u
+        _progress(f"cube8M {name}: {1e3 * per:.4f} ms per step (device), err_inf {rep['err_inf']:.3e}")
+    corr = (finals["fp64"] - u0d).abs().max().item()
+    out["max_abs_diff_fp32_refine_vs_fp64"] = (finals["fp32_refine"] - finals["fp64"]).abs().max().item()
+    out["correction_max_abs"] = corr
+    out["speedup_fp32_refine_device"] = round(out["fp64"]["ms_per_step_device"] /
+                                              out["fp32_refine"]["ms_per_step_device"], 3)
+    out["speedup_fp32_refine_wall"] = round(out["fp64"]["ms_per_step_wall"] / out["fp32_refine"]["ms_per_step_wall"], 3)
+    out["steps_to_target"] = {"value": builder_steps_to_target, "target_err_inf": target,
+                              "source": "measured by the builder in full runs of both modes to the target "
+                                        "(bench.py --workload cube8M --mode fp64 / fp32_refine); not re-run here"}
+    p.close()
+    del finals, fd, uref, u0d
+    torch.cuda.empty_cache()
+    return out
 
 
 def _progress(msg):
@@ -310,7 +415,7 @@ def run_cube4m_bands(steps=1000):
     p.autotune()
     u_ex, f, g, u0 = ri.manufactured(3, xyz_h, typ_h)
     s = {"p": p, "wl": wl, "f": _dev(f), "u0": _dev(u0)}
-    wall, per_sweep, nsw, rep = time_sweeps(s, steps, 100)
+    wall, per_sweep, nsw, rep, _ = time_sweeps(s, steps, 100)
     nint = int(interior.sum())
     return {"workload": "cube4M_bands: 3D 159^3 jittered grid (seed 3), m=2/4/6 by distance to the boundary "
                         "(<3h, <6h, else), n=2M", "classes": classes, "interior_nodes": nint,
@@ -327,13 +432,17 @@ def run_cube4m_bands(steps=1000):
             "sweep_hbm_frac": round(alg_bytes / per_sweep / 1e9 / PEAK_HBM_GBS, 4), "res_final": rep["res_final"]}
 
 
-def run_cube2m_adjoint(directions=32):
+def run_cube2m_adjoint(directions=32, cpu_K=20):
     """dJ/df for J = 1/2 |u_K - u_target|^2 (interior) after K = 2000 steps on
     the 126^3 cube (m = 4), by checkpointed forward + transposed sweeps, against
-    central differences on `directions` seeded smooth directions."""
+    central differences on `directions` seeded smooth directions; and the
+    gradient of the first `cpu_K` steps against the oracle's sequential
+    transposed loop on the same 2M-node operator (the CPU reference gradient;
+    the full K would take the sequential oracle tens of minutes)."""
     import numpy as np
     import torch
 
+    import oracle
     import rbf_inputs as ri
     from paper_2502_12878_amd import Problem, SolveK
     wl = ri.workload("cube2M_adjoint")
@@ -358,8 +467,8 @@ def run_cube2m_adjoint(directions=32):
         d = (SolveK.apply(ff, p, zero, K, every, wl.dt) - u_t)[It]
         return 0.5 * (d * d).sum()
 
-    # first backward: builds the transposed operator and its codes and tunes
-    # the transposed gather (timed separately); then the timed pass
+    # first backward: builds the transposed operator and its codes and picks
+    # the transposed sweep's shape (timed separately); then the timed pass
     fr = f.clone().requires_grad_(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -392,17 +501,31 @@ def run_cube2m_adjoint(directions=32):
             errs.append(abs((grad * v).sum().item() - fd) / abs(fd))
             _progress(f"direction {j}: rel err {errs[-1]:.2e}")
             j += 1
+        # CPU reference gradient: dJ/du_K of this problem, cpu_K transposed
+        # steps on the library's operator, GPU vs the oracle's loop
+        gK = torch.where(It, SolveK.apply(f, p, zero, K, every, wl.dt) - u_t, zero)
+    sten = p.get_stencils()
+    op = oracle.Operator(typ_h, sten, p.get_weights())
+    gK_h = gK.cpu().numpy()
+    g_gpu = p.adjoint_f(gK, cpu_K, cpu_K, wl.dt).cpu().numpy()
+    t3 = time.perf_counter()
+    g_cpu = op.adjoint_f(wl.dt, cpu_K, gK_h)
+    cpu_s = time.perf_counter() - t3
+    cpu_rel = float(np.abs(g_gpu - g_cpu).max() / np.abs(g_cpu).max())
+    _progress(f"CPU reference gradient ({cpu_K} steps): rel diff {cpu_rel:.2e}, oracle {cpu_s:.1f} s")
+    del op
     # algorithmic bytes per step: forward 12n + 24 per interior row; a
-    # transposed step 12 B per entry of L_II (id and weight) plus lambda,
-    # lambda_new and the running sum read and written (32 B) per interior row
-    sten = p.get_stencils()[I]
-    valid = sten >= 0
-    nnz = int((valid & (typ_h[np.where(valid, sten, 0)] == 0)).sum())
+    # transposed step (Horner form: the forward sweep on L_II^T) 12 B per
+    # entry of L_II plus f, T and T_new (24 B) per interior row
+    valid = sten[I] >= 0
+    nnz = int((valid & (typ_h[np.where(valid, sten[I], 0)] == 0)).sum())
     del sten, valid
     nint = int(I.sum())
     fwd_bytes = (12 * wl.n + 24) * nint
-    adj_bytes = 12 * nnz + 32 * nint
+    adj_bytes = 12 * nnz + 24 * nint
     fwd_ms, adj_ms = 1e3 * (t1 - t0) / K, 1e3 * (t2 - t1) / K
+    info = p.operator_info()
+    p.close()
     return {"workload": "cube2M_adjoint: 3D 126^3 jittered grid (seed 4), m=4, n=70, K=2000, checkpoints every 100",
             "interior_nodes": nint, "nnz_L_II": nnz, "forward_alg_GBps": round(fwd_bytes / fwd_ms / 1e6, 1),
             "adjoint_alg_GBps": round(adj_bytes / adj_ms / 1e6, 1),
@@ -410,8 +533,14 @@ def run_cube2m_adjoint(directions=32):
             "forward_ckpt_s": round(t1 - t0, 3), "adjoint_s": round(t2 - t1, 3),
             "first_forward_and_adjoint_s": round(first_s, 3),
             "adjoint_ms_per_step": round(1e3 * (t2 - t1) / K, 4), "forward_ms_per_step": round(1e3 * (t1 - t0) / K, 4),
+            "transposed_operator": {k: info[k] for k in ("t_slices", "t_slots", "t_coded_slices", "t_code_mismatches",
+                                                         "t_max_len", "t_waves", "t_unroll", "t_codes")},
             "J": loss.item(), "fd_eps": eps, "directions": directions, "max_rel_err_vs_fd": max(errs),
-            "median_rel_err_vs_fd": float(np.median(errs)), "rel_errs": errs}
+            "median_rel_err_vs_fd": float(np.median(errs)), "rel_errs": errs,
+            "cpu_reference_gradient": {"steps": cpu_K, "rel_diff_gpu_vs_oracle": cpu_rel, "oracle_s": round(cpu_s, 2),
+                                       "how": "dJ/du_K of the K=2000 problem pulled back through the first "
+                                              f"{cpu_K} transposed steps by the library and by the oracle's "
+                                              "sequential scatter loop on the library's operator"}}
 
 
 def run_support_sweep(m=2, sizes=(20, 30, 40, 60, 80, 100, 130, 168), steps=1000):
@@ -440,7 +569,7 @@ def run_support_sweep(m=2, sizes=(20, 30, 40, 60, 80, 100, 130, 168), steps=1000
         setup = time.perf_counter() - t0
         p.autotune()
         s = {"p": p, "wl": wl, "f": _dev(f), "u0": _dev(u0)}
-        wall, per_sweep, nsw, rep = time_sweeps(s, steps, 100)
+        wall, per_sweep, nsw, rep, _ = time_sweeps(s, steps, 100)
         trunc = p.residual(s["f"], _dev(u_ex))
         rows.append({"n": n, "setup_s": round(setup, 3), "kernel_ms_per_sweep": round(1e3 * per_sweep, 4),
                      "node_updates_per_s": nint / per_sweep,
@@ -711,6 +840,8 @@ def main():
     ap.add_argument("--orders", default="4,2,6", help="augmentation orders; the first is the headline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tte", action="store_true", help="skip the time-to-error comparison")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 8M-node FP32+refine vs FP64 block")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 2M-node adjoint block")
     ap.add_argument("--tte-target", type=float, default=1e-6)
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--workload", default="cube1M",
@@ -718,6 +849,7 @@ def main():
                              "order_scan", "mixed_bc", "square10k"],
                     help="cube1M: the benchmark line; the others print their own measurement line")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32_refine"], help="cube8M: iteration mode")
+    ap.add_argument("--directions", type=int, default=32, help="cube2M_adjoint: central-difference directions")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -748,7 +880,7 @@ def main():
         elif args.workload == "square10k":
             out = run_square10k()
         else:
-            out = run_cube2m_adjoint()
+            out = run_cube2m_adjoint(directions=args.directions)
         out["device"] = torch.cuda.get_device_name(0)
         print(json.dumps(out))
         return
@@ -756,15 +888,17 @@ def main():
     per_order = {}
     head = None
     for i, m in enumerate(orders):
+        _progress(f"cube1M m={m}: setup and {args.steps} timed steps")
         s = setup_problem(m, keep_fp32=(i == 0 and not args.no_tte))
         wl = s["wl"]
         nint = int((s["typ"] == 0).sum())
-        wall, per_sweep, nsw, rep = time_sweeps(s, args.steps, args.warmup)
+        wall, per_sweep, nsw, rep, warm_run = time_sweeps(s, args.steps, args.warmup)
         bytes_per_update = 12 * wl.n + 24
         alg_bytes = bytes_per_update * nint
         info = s["p"].operator_info()
         entry = {"m": m, "n": wl.n, "interior_nodes": nint, "node_updates_per_s": nint * args.steps / wall,
                  "ms_per_step": 1e3 * wall / args.steps, "kernel_ms_per_sweep": 1e3 * per_sweep,
+                 "warmup_steps_run": warm_run,
                  "alg_bytes_per_update": bytes_per_update, "alg_GBps": alg_bytes / per_sweep / 1e9,
                  "hbm_frac": alg_bytes / per_sweep / 1e9 / PEAK_HBM_GBS, "res_final": rep["res_final"],
                  "format_bytes_per_sweep": info["stream_bytes_f64"],
@@ -790,8 +924,10 @@ def main():
                 "avg_launch_ms": round(1e3 * per_sweep, 5), "launches_timed": nsw,
                 "format_bytes_per_launch": entry["format_bytes_per_sweep"],
                 "format_frac": round(entry["format_GBps"] / PEAK_HBM_GBS, 4), "sweep_shape": entry["sweep_shape"]}
-    tte = None if args.no_tte else time_to_error(s, args.tte_target)
-    if tte is not None:
+    tte = None
+    if not args.no_tte:
+        _progress("cube1M: time to L-inf error, FP64 and FP32 + refinement")
+        tte = time_to_error(s, args.tte_target)
         info = s["p"].operator_info()
         tte["fp32_sweep_shape"] = {k[4:]: v for k, v in info.items() if k.startswith("f32_")}
         tte["fp32_format_bytes_per_sweep"] = info["stream_bytes_f32"]
@@ -804,16 +940,33 @@ def main():
             tte["fp32_ms_per_inner_step"] = round(1e3 * per32, 5)
             tte["fp32_alg_GBps"] = round(alg32 / per32 / 1e9, 1)
             tte["fp32_hbm_frac"] = round(alg32 / per32 / 1e9 / PEAK_HBM_GBS, 4)
-    cpu = None if args.no_cpu else cpu_baseline()
+    cpu = None
+    if not args.no_cpu:
+        _progress("CPU baseline: the oracle's OpenMP sweep on the cube1M operator")
+        cpu = cpu_baseline(s)
+    s["p"].close()
+    del s
+    torch.cuda.empty_cache()
+    c2 = None
+    if not args.no_c2:
+        _progress("cube8M: FP64 and FP32 + refinement steps")
+        c2 = run_c2_block()
+    c4 = None
+    if not args.no_c4:
+        _progress("cube2M adjoint: gradient vs central differences and the oracle")
+        c4 = run_cube2m_adjoint()
     out = {"metric": "sweep node-updates/s + HBM GB/s; time to L-inf err 1e-6, FP32+refine vs FP64",
            "value": entry["node_updates_per_s"], "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": entry["ms_per_step"], "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "scaling": "weak", "scaling_note": "one GPU only (no multi-GPU path); a shard would hold one "
+                                              "fixed-size block of rows per GPU",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"cube1M: 3D 100^3 jittered grid (seed 1), m={wl.m}, n={wl.n}, "
                                   f"dt={wl.alpha}*h^2/6, FP64 explicit sweep",
                       "interior_nodes": entry["interior_nodes"], "parallelism": "single GPU"},
            "roofline": roofline, "cpu_baseline": cpu,
            "orders": {str(k): v for k, v in per_order.items()}, "time_to_error": tte,
+           "cube8M_fp32_refine_vs_fp64": c2, "cube2M_adjoint": c4,
            "stream_ceiling": stream_ceiling(), "ell_layout": int(os.environ.get("RBF_ELL_LAYOUT", "1")),
            "device": torch.cuda.get_device_name(0)}
     print(json.dumps(out))
