@@ -230,6 +230,21 @@ rbf_status rbf_apply_transpose(rbf_handle *h, const double *v_dev, double *out_d
  * Synchronises. */
 rbf_status rbf_residual(rbf_handle *h, const double *f_dev, const double *u_dev, double *res_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the result
+ * of rbf_residual, max|L u - f| over interior nodes, written to the device
+ * double *res_dev.  Queued on the handle's stream without synchronising; no
+ * allocation of any kind.  The gathered copies of u and f and the reduction
+ * slot live in a static workspace of 32 MiB that the library holds on each
+ * device it runs on until the process ends, so the node count is limited to
+ * 2^21 = 2,097,152 (EINVAL beyond, naming the limit).  Every call on a device
+ * shares that workspace: calls that overlap on one device (other streams,
+ * other handles, other host threads) race and must be serialised by the
+ * caller.  f_dev, u_dev: [N] device, canonical order; res_dev: one device
+ * double.  EINVAL without an operator or with NULL pointers; EHIP when the
+ * workspace address could not be found on this device. */
+rbf_status rbf_residual_noalloc(rbf_handle *h, const double *f_dev, const double *u_dev, double *res_dev);
+
 /* ---------------------------------------- adjoint (inverse source problems) */
 
 /* K explicit steps from u0 (Dirichlet values included) with checkpoints:

@@ -186,6 +186,18 @@ class Problem:
         self._check(self._lib.rbf_residual(self.h, _ptr(f), _ptr(u), C.byref(r)), "residual")
         return r.value
 
+    def residual_noalloc(self, f, u, out=None):
+        """max|L u - f| into the one-element device tensor ``out`` (created if
+        None) by the no-allocation entry point: asynchronous on the handle's
+        stream; at most 2^21 nodes; concurrent calls on one device race."""
+        torch = self.torch
+        f = self._cuda(f, torch.float64)
+        u = self._cuda(u, torch.float64)
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.device)
+        self._check(self._lib.rbf_residual_noalloc(self.h, _ptr(f), _ptr(u), _ptr(out)), "residual_noalloc")
+        return out
+
     # ------------------------------------------------------------------ iteration
     def iterate(self, f, u, dt, max_steps, tol_rel=0.0, chunk=500, mode=RBF_MODE_FP64, inner_steps=500,
                 stall_chunks=0, u_ref=None, err_target=0.0):

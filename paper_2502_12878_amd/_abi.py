@@ -83,6 +83,7 @@ SIGNATURES = {
     "rbf_apply": (_st, [_h, _p, _p]),
     "rbf_apply_transpose": (_st, [_h, _p, _p]),
     "rbf_residual": (_st, [_h, _p, _p, C.POINTER(C.c_double)]),
+    "rbf_residual_noalloc": (_st, [_h, _p, _p, _p]),
     "rbf_forward_ckpt": (_st, [_h, _p, _p, C.c_int64, C.c_int64, _p, _p, C.c_double]),
     "rbf_adjoint_f": (_st, [_h, _p, C.c_int64, C.c_int64, _p, _p, C.c_double]),
     "rbf_get_stencils": (_st, [_h, _p]),

@@ -468,6 +468,16 @@ hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *perm, const d
     return hipGetLastError();
 }
 
+// *out = the double whose IEEE bits a max-reduction slot holds.
+__global__ void k_slot_to_double(const unsigned long long *__restrict__ slot, double *__restrict__ out) {
+    if (threadIdx.x == 0) *out = __longlong_as_double((long long)*slot);
+}
+
+hipError_t launch_slot_to_double(hipStream_t s, const unsigned long long *slot, double *out) {
+    hipLaunchKernelGGL(k_slot_to_double, dim3(1), dim3(64), 0, s, slot, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_f64(hipStream_t s, int64_t n, double v, double *p) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill<double>, dim3(grid1d(n, 256)), dim3(256), 0, s, n, v, p);

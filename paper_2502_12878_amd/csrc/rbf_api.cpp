@@ -14,6 +14,7 @@
 #include <cstring>
 #include <fstream>
 #include <limits>
+#include <mutex>
 #include <numeric>
 #include <sstream>
 #include <string>
@@ -286,6 +287,39 @@ const char *rbf_status_string(rbf_status s) {
 
 const char *rbf_last_error(const rbf_handle *h) { return h ? h->err.c_str() : "null handle"; }
 
+// Workspace of rbf_residual_noalloc (for callers that cannot allocate): the
+// iterate and the source in internal order, kNoAllocMaxNodes doubles each,
+// then the max-residual slot.  A file-scope device array, so every device the
+// library runs on holds one copy (32 MiB + 256 B) until the process ends.
+// Host code never uses the array's name as an address: its device address is
+// looked up once per device (hipGetSymbolAddress, with that device current)
+// when the first handle on the device is created, and kept in g_noalloc_ws.
+constexpr int64_t kNoAllocMaxNodes = (int64_t)1 << 21;
+constexpr int64_t kNoAllocDoubles = 2 * kNoAllocMaxNodes + 32;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+static std::mutex g_noalloc_mu;
+static double *g_noalloc_ws[kNoAllocMaxDevices];
+
+// Look up this device's workspace address (the device is current).
+static hipError_t init_noalloc_workspace(int device) {
+    if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ws[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_noalloc_ws[device] = static_cast<double *>(ptr);
+    return hipSuccess;
+}
+
+static double *noalloc_workspace(int device) {
+    if (device < 0 || device >= kNoAllocMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    return g_noalloc_ws[device];
+}
+
 rbf_status rbf_create(rbf_handle **out, int device, void *hip_stream, const rbf_allocator *alloc) {
     if (!out) return RBF_EINVAL;
     *out = nullptr;
@@ -307,6 +341,9 @@ rbf_status rbf_create(rbf_handle **out, int device, void *hip_stream, const rbf_
     }
     std::snprintf(h->arch, sizeof h->arch, "%s", prop.gcnArchName);
     h->num_cus = prop.multiProcessorCount;
+    // the no-allocation entry point's workspace on this device (a failure
+    // here only disables that entry point, which then reports it)
+    h->noalloc_status = init_noalloc_workspace(device);
     if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&h->cap2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&h->evf[0], hipEventDisableTiming) != hipSuccess ||
@@ -1185,6 +1222,34 @@ extern "C" rbf_status rbf_residual(rbf_handle *h, const double *f_dev, const dou
     HIPCHK(h, launch_gather(h->stream, h->N, h->perm, u_dev, h->ua));
     HIPCHK(h, launch_gather(h->stream, h->N, h->perm, f_dev, h->fint));
     return residual_internal(h, h->ua, res_host);
+}
+
+// rbf_residual without allocating and without synchronising: the same
+// gathers into internal order and the same residual kernel, with the staging
+// vectors and the reduction slot in the static per-device workspace instead
+// of the handle's buffers; the result goes to a device double.
+extern "C" rbf_status rbf_residual_noalloc(rbf_handle *h, const double *f_dev, const double *u_dev, double *res_dev) {
+    if (!h) return RBF_EINVAL;
+    h->err.clear();
+    if (!h->have_w || !h->ua) return fail(h, RBF_EINVAL, "no operator");
+    if (!f_dev || !u_dev || !res_dev) return fail(h, RBF_EINVAL, "null pointer");
+    if (h->N > kNoAllocMaxNodes)
+        return fail(h, RBF_EINVAL,
+                    "rbf_residual_noalloc: %" PRId64 " nodes exceed its static workspace (at most %" PRId64 " nodes)",
+                    h->N, kNoAllocMaxNodes);
+    double *ws = noalloc_workspace(h->device);
+    if (!ws)
+        return fail(h, RBF_EHIP, "rbf_residual_noalloc: workspace address unavailable on device %d (%s)", h->device,
+                    hipGetErrorString(h->noalloc_status));
+    DeviceGuard g(h->device);
+    double *u_int = ws, *f_int = ws + kNoAllocMaxNodes;
+    unsigned long long *slot = reinterpret_cast<unsigned long long *>(ws + 2 * kNoAllocMaxNodes);
+    HIPCHK(h, launch_gather(h->stream, h->N, h->perm, u_dev, u_int));
+    HIPCHK(h, launch_gather(h->stream, h->N, h->perm, f_dev, f_int));
+    HIPCHK(h, launch_fill_u64(h->stream, 1, 0ull, slot));  // the slot keeps the previous call's maximum
+    if (h->N_int) HIPCHK(h, launch_apply_f64(h->stream, h->cfg, h->ell, h->N_int, u_int, nullptr, f_int, slot));
+    HIPCHK(h, launch_slot_to_double(h->stream, slot, res_dev));
+    return RBF_OK;
 }
 
 // ====================================================================== graphs

@@ -136,6 +136,7 @@ struct rbf_handle {
     rbf::SweepCfg cfgT;   // sweep on the transposed operator (adjoint)
     bool tunedT = false;
     int weights_panel = 16;
+    hipError_t noalloc_status = hipSuccess;  // lookup of the no-allocation workspace at creation
     double last_sweep_sec = 0.0;
     int64_t last_sweeps = 0;
 
@@ -237,6 +238,7 @@ hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *perm, const d
 hipError_t launch_fill_f64(hipStream_t s, int64_t n, double v, double *p);
 hipError_t launch_fill_f32(hipStream_t s, int64_t n, float v, float *p);
 hipError_t launch_fill_u64(hipStream_t s, int64_t n, unsigned long long v, unsigned long long *p);
+hipError_t launch_slot_to_double(hipStream_t s, const unsigned long long *slot, double *out);
 hipError_t launch_scale_interior(hipStream_t s, int64_t N, int64_t N_int, double a, const double *src, double *dst);
 
 }  // namespace rbf
