@@ -145,10 +145,19 @@ rbf_status rbf_build_stencils(rbf_handle *h, int32_t n_uniform, const int16_t *n
  * such systems, else 16; RBF_WEIGHTS_PANEL=8 or 16 fixes it.  Every width
  * performs the same floating-point operations in the same order, so the
  * weights do not depend on it.
+ * With RBF_WEIGHTS_SOLVER=ns in the environment, systems with m >= 1 that
+ * fit the workgroup's LDS are solved by a null-space method instead (the
+ * constraint rows eliminated through a factorisation of P, the remaining
+ * symmetric positive definite system by Cholesky): the same solution in
+ * another operation order, agreeing with the elimination to ~1e-12 relative
+ * per row rather than bitwise.  rbf_get_operator_info reports how many
+ * systems each solver took.
  * Synchronises.  ESINGULAR (with the node id in rbf_last_error) when a pivot
  * is zero or below 2^-45 times the largest matrix entry (a support with fewer
- * nodes than monomials, duplicate or collinear nodes); EINVAL when m is not
- * in 0..6 or no stencils are set. */
+ * nodes than monomials, duplicate or collinear nodes; on the null-space path
+ * a pivot of the factorisation of P at most 2^-45 max|P| or a Cholesky pivot
+ * at most 2^-45 times the largest diagonal entry); EINVAL when m is not in
+ * 0..6 or no stencils are set. */
 rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, const int8_t *m_per_node_dev, int keep_fp32);
 
 /* ------------------------------------------------------ iterate (Sec. II-C) */
@@ -330,6 +339,8 @@ typedef struct {
     int64_t t_slices, t_slots, t_coded_slices, t_code_mismatches;
     int32_t t_max_len;                   /* longest transposed row (largest interior in-degree, even) */
     int32_t t_waves, t_unroll, t_codes;  /* launch shape of the transposed sweep */
+    int64_t ns_systems;     /* weight systems solved by the null-space solver (last rbf_compute_weights) */
+    int64_t elim_systems;   /* weight systems solved by Gaussian elimination (same call)               */
 } rbf_operator_info;
 
 /* Fill *info for the current operator (EINVAL without one). */

@@ -25,6 +25,7 @@ SOURCES = {
     "k_nodes.hip": ["-ffp-contract=off"],
     "k_knn.hip": ["-ffp-contract=off"],
     "k_weights.hip": ["-ffp-contract=off"],
+    "k_weights_ns.hip": [],
     "k_transpose.hip": [],
     "rbf_api.cpp": [],
 }

@@ -872,6 +872,14 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
 }
 
 // ====================================================================== weights
+// RBF_WEIGHTS_SOLVER=ns: the null-space solver where it applies; unset or
+// "gepp": every system larger than the one-wavefront size by the blocked
+// elimination in the oracle's operation order (bit-equal to the oracle).
+static bool weights_solver_ns() {
+    const char *v = std::getenv("RBF_WEIGHTS_SOLVER");
+    return v && std::strcmp(v, "ns") == 0;
+}
+
 extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, const int8_t *m_per_node_dev,
                                           int keep_fp32) {
     if (!h) return RBF_EINVAL;
@@ -904,29 +912,93 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
     std::vector<int8_t> mrows;
     const size_t isz = weights_item_bytes();
     std::vector<char> items;
+    // null-space systems: one launch per register chunk size (items, largest
+    // system's LDS in doubles)
+    std::map<int, std::pair<std::vector<char>, int>> ns_launch;
     int S_small = 0, S_large = 0;
-    int64_t nitems = 0, nlarge = 0;
+    int64_t nitems = 0, nlarge = 0, nitems_ns = 0;
+    const bool ns_on = weights_solver_ns();
+    size_t lds_limit = 0;
+    {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess)
+            lds_limit = (size_t)v;
+    }
     for (auto &c : order) {
         // systems of at most weights_small_limit() unknowns: one wavefront
-        // each, matrix in LDS; larger ones: blocked, one workgroup each
-        const int kind = c.S <= weights_small_limit() ? 0 : 1;
+        // each, matrix in LDS; larger ones with m >= 1 whose working set fits
+        // the null-space solver's LDS layout: that solver, one workgroup each;
+        // the rest: blocked elimination, one workgroup each
+        int kind = c.S <= weights_small_limit() ? 0 : 1;
+        if (kind == 1 && ns_on && c.m >= 1 && ns_fits(c.n, c.S - c.n, lds_limit - 64)) kind = 2;
         if (kind == 0) S_small = std::max(S_small, c.S);
         if (kind == 1) S_large = std::max(S_large, c.S);
+        const int rc = kind == 2 ? ns_rows_per_chunk(c.n) : 0;
+        if (kind == 2) {
+            int &mx = ns_launch[rc].second;
+            mx = std::max(mx, ns_layout_host(c.n, c.S - c.n, rc).total);
+        }
         const int per = kind == 0 ? 4 : 1;
         const int64_t first = (int64_t)rows.size();
         for (int32_t r : *c.rows) {
             rows.push_back(r);
             mrows.push_back((int8_t)c.m);
         }
+        std::vector<char> &dst = kind == 2 ? ns_launch[rc].first : items;
         for (int64_t q = 0; q < (int64_t)c.rows->size(); q += per) {
-            items.resize(items.size() + isz);
-            weights_make_item(items.data() + items.size() - isz, kind, (int)std::min<int64_t>(per, c.rows->size() - q), first + q);
-            ++nitems;
-            nlarge += kind == 1;
+            dst.resize(dst.size() + isz);
+            weights_make_item(dst.data() + dst.size() - isz, kind == 2 ? 1 : kind,
+                              (int)std::min<int64_t>(per, c.rows->size() - q), first + q);
+            if (kind == 2) {
+                ++nitems_ns;
+            } else {
+                ++nitems;
+                nlarge += kind == 1;
+            }
         }
     }
+    h->w_ns_systems = nitems_ns;
+    h->w_elim_systems = (int64_t)rows.size() - nitems_ns;
     ALLOC(h, h->w_can, double, (size_t)N * h->n_max);
     HIPCHK(h, launch_fill_f64(h->stream, N * (int64_t)h->n_max, 0.0, h->w_can));
+    if (nitems_ns > 0) {
+        // null-space systems (one persistent launch per chunk size), before the others
+        int32_t *d_rows = nullptr, *counter = nullptr;
+        int8_t *d_m = nullptr;
+        ALLOC(h, d_rows, int32_t, rows.size());
+        ALLOC(h, d_m, int8_t, mrows.size());
+        ALLOC(h, counter, int32_t, 4);
+        HIPCHK(h, hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(d_m, mrows.data(), mrows.size(), hipMemcpyHostToDevice, h->stream));
+        rbf_status st = reset_status(h);
+        if (st) return st;
+        std::vector<char *> d_items;
+        for (auto &kv : ns_launch) {
+            const std::vector<char> &its = kv.second.first;
+            char *di = nullptr;
+            ALLOC(h, di, char, its.size());
+            d_items.push_back(di);
+            HIPCHK(h, hipMemcpyAsync(di, its.data(), its.size(), hipMemcpyHostToDevice, h->stream));
+            const size_t lds = ((size_t)kv.second.second * sizeof(double) + 255) & ~(size_t)255;
+            const int grid = weights_ns_grid(dim, kv.first, lds);
+            if (grid <= 0) return fail(h, RBF_EHIP, "null-space weight solver does not fit on the device");
+            HIPCHK(h, launch_fill_u64(h->stream, 1, 0ull, (unsigned long long *)counter));
+            HIPCHK(h, launch_weights_ns(h->stream, dim, kv.first, N, h->xyz, h->sten, h->nrow, h->n_max, d_rows, d_m,
+                                        h->type, h->normals, h->w_can, h->dstatus, di,
+                                        (int64_t)(its.size() / isz), counter, lds, grid));
+        }
+        DevStatus ds;
+        st = read_status(h, &ds);
+        dfree(h, d_rows);
+        dfree(h, d_m);
+        for (char *di : d_items) dfree(h, di);
+        dfree(h, counter);
+        if (st) return st;
+        if (ds.code != 0) {
+            free_t(h, h->w_can);
+            return fail(h, ds.code, "singular local system at node %" PRId64, ds.info);
+        }
+    }
     if (nitems > 0) {
         int32_t *d_rows = nullptr, *counter = nullptr;
         int8_t *d_m = nullptr;
@@ -1080,6 +1152,7 @@ extern "C" rbf_status rbf_set_stencils(rbf_handle *h, const int32_t *idx_host, i
 extern "C" rbf_status rbf_set_weights(rbf_handle *h, const double *w_host, int keep_fp32) {
     if (!h) return RBF_EINVAL;
     h->err.clear();
+    h->w_ns_systems = h->w_elim_systems = 0;
     if (!h->have_sten) return fail(h, RBF_EINVAL, "no stencils set");
     if (!w_host) return fail(h, RBF_EINVAL, "null weights");
     const int64_t N = h->N, nm = h->n_max;
@@ -1595,6 +1668,8 @@ extern "C" rbf_status rbf_get_operator_info(const rbf_handle *h, rbf_operator_in
         info->t_unroll = h->cfgT.unroll;
         info->t_codes = h->cfgT.codes && t.cmode ? 1 : 0;
     }
+    info->ns_systems = h->w_ns_systems;
+    info->elim_systems = h->w_elim_systems;
     return RBF_OK;
 }
 
