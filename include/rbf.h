@@ -133,25 +133,31 @@ rbf_status rbf_build_stencils(rbf_handle *h, int32_t n_uniform, const int16_t *n
  * polyharmonic spline phi(r) = r^3 plus all monomials of total degree <= m
  * (M = C(m+d, d), graded, x exponent then y exponent descending).  The system
  * is built in local coordinates y = (x - x_c)/s, s = the largest support
- * distance, solved in FP64 by Gaussian elimination with partial pivoting
- * (first row of largest |a_ik|), and w = x/(s*s).  Neumann rows get the
- * weights of the derivative along their normal nv instead: right-hand side
+ * distance, solved in FP64, and w = x/(s*s).  Neumann rows get the weights of
+ * the derivative along their normal nv instead: right-hand side
  * 3|y_k| ((0 - y_k) . nv) and nv_a for the monomial y_a, w = x/s.
  * m_uniform: order for every node, or -1 with m_per_node_dev ([N] int8).
  * keep_fp32: also keep an FP32 copy (needed by the mixed-precision mode).
- * Systems larger than 40 unknowns are factored by panels of 8 or 16
- * columns; the panel width is read from the tuning cache (key
- * weights|arch|dim|S), else timed on a sample when there are at least 4096
- * such systems, else 16; RBF_WEIGHTS_PANEL=8 or 16 fixes it.  Every width
- * performs the same floating-point operations in the same order, so the
- * weights do not depend on it.
- * With RBF_WEIGHTS_SOLVER=ns in the environment, systems with m >= 1 that
- * fit the workgroup's LDS are solved by a null-space method instead (the
- * constraint rows eliminated through a factorisation of P, the remaining
- * symmetric positive definite system by Cholesky): the same solution in
- * another operation order, agreeing with the elimination to ~1e-12 relative
- * per row rather than bitwise.  rbf_get_operator_info reports how many
- * systems each solver took.
+ * Solvers:
+ * - systems of more than 40 unknowns with m >= 1, 2 or 3 dimensions,
+ *   n <= 255 and M, n - M + 1 <= 88 (3D) or 64 (2D): a null-space method.
+ *   P = [L1; L2] U by LU with partial pivoting (rows reordered pivots
+ *   first), w = v + G z with G = [-L1^{-T} L2^T; I] spanning the null space
+ *   of P^T and P^T v = Lp, and (G^T A G) z = G^T (L Phi - A v) by Cholesky
+ *   (G^T A G is positive definite since r^3 is conditionally positive
+ *   definite of order 2).  The same solution in another operation order: it
+ *   agrees with the elimination to ~1e-12 relative per row, not bitwise;
+ * - every other system: Gaussian elimination with partial pivoting (first row
+ *   of largest |a_ik|) in the oracle's operation order, bit-equal to it.
+ *   Above 40 unknowns it is factored by panels of 8 or 16 columns; the panel
+ *   width is read from the tuning cache (key weights|arch|dim|S), else timed
+ *   on a sample when there are at least 4096 such systems, else 16;
+ *   RBF_WEIGHTS_PANEL=8 or 16 fixes it.  Every width performs the same
+ *   floating-point operations in the same order, so the weights do not
+ *   depend on it.
+ * RBF_WEIGHTS_SOLVER=gepp in the environment sends every system to the
+ * elimination.  rbf_get_operator_info reports how many systems each solver
+ * took.
  * Synchronises.  ESINGULAR (with the node id in rbf_last_error) when a pivot
  * is zero or below 2^-45 times the largest matrix entry (a support with fewer
  * nodes than monomials, duplicate or collinear nodes; on the null-space path

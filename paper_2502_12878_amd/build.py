@@ -26,6 +26,11 @@ SOURCES = {
     "k_knn.hip": ["-ffp-contract=off"],
     "k_weights.hip": ["-ffp-contract=off"],
     "k_weights_ns.hip": [],
+    # null-space kernel sizes: row arrays indexed by fully unrolled loops
+    "k_weights_ns_3d88.hip": ["-mllvm", "-pragma-unroll-threshold=2000000"],
+    "k_weights_ns_3d64.hip": ["-mllvm", "-pragma-unroll-threshold=2000000"],
+    "k_weights_ns_3d40.hip": ["-mllvm", "-pragma-unroll-threshold=2000000"],
+    "k_weights_ns_2d.hip": ["-mllvm", "-pragma-unroll-threshold=2000000"],
     "k_transpose.hip": [],
     "rbf_api.cpp": [],
 }

@@ -1,0 +1,8 @@
+// Compiled sizes of the null-space weight kernel: 3D with 88-entry row arrays.
+#include "weights_ns_impl.h"
+
+namespace rbf {
+
+RBF_NS_INSTANCE(3, 88)
+
+}  // namespace rbf

@@ -872,12 +872,12 @@ static rbf_status finalize_operator(rbf_handle *h, int keep_fp32) {
 }
 
 // ====================================================================== weights
-// RBF_WEIGHTS_SOLVER=ns: the null-space solver where it applies; unset or
-// "gepp": every system larger than the one-wavefront size by the blocked
-// elimination in the oracle's operation order (bit-equal to the oracle).
+// RBF_WEIGHTS_SOLVER=gepp: every system larger than the one-wavefront size
+// by the blocked elimination in the oracle's operation order (bit-equal to
+// the oracle); unset or "ns": the null-space solver where it applies.
 static bool weights_solver_ns() {
     const char *v = std::getenv("RBF_WEIGHTS_SOLVER");
-    return v && std::strcmp(v, "ns") == 0;
+    return !(v && std::strcmp(v, "gepp") == 0);
 }
 
 extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, const int8_t *m_per_node_dev,
@@ -912,7 +912,7 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
     std::vector<int8_t> mrows;
     const size_t isz = weights_item_bytes();
     std::vector<char> items;
-    // null-space systems: one launch per register chunk size (items, largest
+    // null-space systems: one launch per register-array size (items, largest
     // system's LDS in doubles)
     std::map<int, std::pair<std::vector<char>, int>> ns_launch;
     int S_small = 0, S_large = 0;
@@ -930,13 +930,13 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
         // the null-space solver's LDS layout: that solver, one workgroup each;
         // the rest: blocked elimination, one workgroup each
         int kind = c.S <= weights_small_limit() ? 0 : 1;
-        if (kind == 1 && ns_on && c.m >= 1 && ns_fits(c.n, c.S - c.n, lds_limit - 64)) kind = 2;
+        if (kind == 1 && ns_on && c.m >= 1 && ns_fits(dim, c.n, c.S - c.n, lds_limit - 64)) kind = 2;
         if (kind == 0) S_small = std::max(S_small, c.S);
         if (kind == 1) S_large = std::max(S_large, c.S);
-        const int rc = kind == 2 ? ns_rows_per_chunk(c.n) : 0;
+        const int bucket = kind == 2 ? ns_bucket(dim, c.n, c.S - c.n) : 0;
         if (kind == 2) {
-            int &mx = ns_launch[rc].second;
-            mx = std::max(mx, ns_layout_host(c.n, c.S - c.n, rc).total);
+            int &mx = ns_launch[bucket].second;
+            mx = std::max(mx, ns_lds_doubles(c.n, c.S - c.n, bucket));
         }
         const int per = kind == 0 ? 4 : 1;
         const int64_t first = (int64_t)rows.size();
@@ -944,7 +944,7 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
             rows.push_back(r);
             mrows.push_back((int8_t)c.m);
         }
-        std::vector<char> &dst = kind == 2 ? ns_launch[rc].first : items;
+        std::vector<char> &dst = kind == 2 ? ns_launch[bucket].first : items;
         for (int64_t q = 0; q < (int64_t)c.rows->size(); q += per) {
             dst.resize(dst.size() + isz);
             weights_make_item(dst.data() + dst.size() - isz, kind == 2 ? 1 : kind,
@@ -962,7 +962,7 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
     ALLOC(h, h->w_can, double, (size_t)N * h->n_max);
     HIPCHK(h, launch_fill_f64(h->stream, N * (int64_t)h->n_max, 0.0, h->w_can));
     if (nitems_ns > 0) {
-        // null-space systems (one persistent launch per chunk size), before the others
+        // null-space systems (one persistent launch per register-array size), before the others
         int32_t *d_rows = nullptr, *counter = nullptr;
         int8_t *d_m = nullptr;
         ALLOC(h, d_rows, int32_t, rows.size());

@@ -196,17 +196,13 @@ hipError_t launch_weights_items(hipStream_t s, int dim, int64_t N, const double 
                                 int32_t *counter, int S_small, int S_large, int grid, int nslabs,
                                 size_t *lds_used);
 
-// Null-space solver (k_weights_ns.hip) for systems with m >= 1 that fit its
-// LDS layout: offsets in doubles of one system's working set.
-struct NsLayout {
-    int n, M, K, R, ldz, nJ, nA;
-    int big, ablk, tblk, y, b1, b2, y1, rhs, tau, misc, total;
-};
-int ns_rows_per_chunk(int n);                  // rows per register chunk (12, 24, 44; 0: n too large)
-NsLayout ns_layout_host(int n, int M, int rc);  // layout of a system in a launch with chunk size rc
-bool ns_fits(int n, int M, size_t lds_limit);
-int weights_ns_grid(int dim, int rc, size_t lds_bytes);
-hipError_t launch_weights_ns(hipStream_t s, int dim, int rc, int64_t N, const double *xyz, const int32_t *sten,
+// Null-space solver (k_weights_ns.hip) for systems with m >= 1 whose sizes
+// fit its register arrays and LDS layout; one launch per register-array size.
+int ns_bucket(int dim, int n, int M);         // register-array size of the launch for (n, M); 0: no fit
+int ns_lds_doubles(int n, int M, int bucket);  // LDS of one system, in doubles
+bool ns_fits(int dim, int n, int M, size_t lds_limit);
+int weights_ns_grid(int dim, int bucket, size_t lds_bytes);
+hipError_t launch_weights_ns(hipStream_t s, int dim, int bucket, int64_t N, const double *xyz, const int32_t *sten,
                              const int16_t *nrow, int32_t n_max, const int32_t *rows, const int8_t *mrow,
                              const int8_t *type, const double *normals, double *w_out, DevStatus *status,
                              const void *items, int64_t nitems, int32_t *counter, size_t lds_bytes, int grid);

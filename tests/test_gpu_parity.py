@@ -94,6 +94,7 @@ def test_weights_panel_widths_agree_bitwise(m, n, monkeypatch):
     """Systems above 112 unknowns are factored by panels of 8 or 16 columns;
     both widths perform the same operations in the same order, so the
     weights are bitwise equal (and match the oracle within the bar)."""
+    monkeypatch.setenv("RBF_WEIGHTS_SOLVER", "gepp")
     xyz, typ = ri.jittered_grid(3, 11, 0.3, 40 + m)
     got = {}
     for panel in (8, 16):
@@ -115,10 +116,11 @@ def test_weights_panel_widths_agree_bitwise(m, n, monkeypatch):
     assert rel <= 1e-10
 
 
-def test_weights_all_solver_paths_in_one_launch():
-    """One launch with systems of 30 unknowns (one wavefront each, matrix in
-    LDS), 105 unknowns (panel rows in registers) and 266 unknowns (more than
-    256 rows: panels staged in LDS), interleaved over the nodes."""
+def test_weights_all_solver_paths_in_one_launch(monkeypatch):
+    """One elimination launch with systems of 30 unknowns (one wavefront each,
+    matrix in LDS), 105 unknowns (panel rows in registers) and 266 unknowns
+    (more than 256 rows: panels staged in LDS), interleaved over the nodes."""
+    monkeypatch.setenv("RBF_WEIGHTS_SOLVER", "gepp")
     xyz, typ = ri.jittered_grid(3, 11, 0.3, 21)
     N = len(typ)
     interior = np.nonzero(typ == 0)[0]
@@ -159,11 +161,13 @@ def test_weights_mixed_orders_one_launch():
     assert _rel_rows(wg[I], w[I]) <= 1e-10
 
 
-def test_weights_mixed_orders_with_panel_timing():
-    """Mixed orders with more than 4096 order-6 systems: the solver first times
-    its panel widths on LARGE items only (fewer LDS bytes, more resident
-    workgroups than the full launch), then solves everything.  Regression test
-    for sizing the per-workgroup scratch for the larger of the two grids."""
+def test_weights_mixed_orders_with_panel_timing(monkeypatch):
+    """Mixed orders with more than 4096 order-6 systems on the elimination
+    path: the solver first times its panel widths on LARGE items only (fewer
+    LDS bytes, more resident workgroups than the full launch), then solves
+    everything.  Regression test for sizing the per-workgroup scratch for the
+    larger of the two grids."""
+    monkeypatch.setenv("RBF_WEIGHTS_SOLVER", "gepp")
     side = 26
     xyz, typ = ri.jittered_grid(3, side, 0.3, 13)
     m, n = ri.order_bands(3, xyz, typ, ri.grid_spacing(side), inner=2.0, outer=4.0)

@@ -3,9 +3,8 @@ wavefront's, m >= 1): the weights of the augmented system (Sec. II) against
 the oracle's Gaussian elimination, per row within 1e-10 relative (the bar;
 the two solve the same nonsingular system in different operation orders),
 the normal-derivative rows of the mixed boundary variant, the elimination
-path (the default, RBF_WEIGHTS_SOLVER unset) still bit-equal to the oracle,
-and repeated runs bit-equal to each other.  RBF_WEIGHTS_SOLVER=ns selects the
-null-space solver."""
+path (RBF_WEIGHTS_SOLVER=gepp) still bit-equal to the oracle, and repeated
+runs bit-equal to each other."""
 import numpy as np
 import pytest
 
@@ -13,11 +12,6 @@ import oracle
 import rbf_inputs as ri
 
 pytestmark = pytest.mark.gpu
-
-
-@pytest.fixture(autouse=True)
-def _ns_solver(monkeypatch):
-    monkeypatch.setenv("RBF_WEIGHTS_SOLVER", "ns")
 
 
 def _rel_rows(a, b):
@@ -71,9 +65,9 @@ def test_elimination_path_still_bit_equal_and_ns_repeatable(monkeypatch):
     _, w1, _ = _weights(xyz, typ, 70, 4)
     _, w2, _ = _weights(xyz, typ, 70, 4)
     assert np.array_equal(w1, w2)
-    monkeypatch.delenv("RBF_WEIGHTS_SOLVER")
+    monkeypatch.setenv("RBF_WEIGHTS_SOLVER", "gepp")
     idx, we, info = _weights(xyz, typ, 70, 4)
-    monkeypatch.setenv("RBF_WEIGHTS_SOLVER", "ns")
+    monkeypatch.delenv("RBF_WEIGHTS_SOLVER")
     assert info["ns_systems"] == 0 and info["elim_systems"] == len(I)
     wo, _, _, _ = oracle.weights(xyz, idx[I], I, m=4)
     assert np.array_equal(we[I], wo)
