@@ -85,12 +85,12 @@ __host__ __device__ inline LuLayout lu_layout(int n, int M, int B) {
     L.ints = o;                // int32 pivot rows [M], non-pivot rows [K]
     o += (n + 1) / 2 + 1;
     o += o & 1;
-    L.vec = o;                 // rhs [B], L^{-1} r [B], z [B], diag L [B]
+    L.vec = o;                 // rhs [B], L^{-1} r [B], z [B], 1 / diag L [B]
     o += 4 * B;
     L.misc = o;
     o += 64;
     L.xreg = o;                // LU candidate rows, then L1, then [X v1]
-    int xr = 2 * kLW * (B + 2);
+    int xr = 8 * kLW + 2 * kLW * B;
     if (l1_off(M) + 2 > xr) xr = l1_off(M) + 2;
     if (M * L.ldx > xr) xr = M * L.ldx;
     o += xr + (xr & 1);
@@ -103,15 +103,18 @@ __host__ __device__ inline LuLayout lu_layout(int n, int M, int B) {
     return L;
 }
 
-// Lane exchange within each half-wave by ds_swizzle (bit mode: lane ^ X),
-// which needs no address registers.
-template <int X>
-__device__ __forceinline__ double swz_xor(double v) {
-    constexpr int pat = 0x1F | (X << 10);
-    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), pat);
-    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), pat);
+// Lane exchange inside rows of 16 lanes by DPP (quad permutations and row
+// mirrors): ALU latency, no LDS round trip.  All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i within 8
+constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i within 16
 
 __device__ __forceinline__ double lane_value(double v, int l) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
@@ -119,25 +122,23 @@ __device__ __forceinline__ double lane_value(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
-// Maximum over the wavefront, the same value on every lane.
+// Maximum over the wavefront, the same value on every lane: within each row
+// of 16 (pairs, quads, halves, rows), then the four rows.
 __device__ __forceinline__ double wave_max(double v) {
-    v = fmax(v, swz_xor<1>(v));
-    v = fmax(v, swz_xor<2>(v));
-    v = fmax(v, swz_xor<4>(v));
-    v = fmax(v, swz_xor<8>(v));
-    v = fmax(v, swz_xor<16>(v));
-    return fmax(lane_value(v, 0), lane_value(v, 32));
+    v = fmax(v, dpp_f64<kDppXor1>(v));
+    v = fmax(v, dpp_f64<kDppXor2>(v));
+    v = fmax(v, dpp_f64<kDppHalfMirror>(v));
+    v = fmax(v, dpp_f64<kDppMirror>(v));
+    return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
 }
 
-// Sum over the wavefront (butterfly within the halves, then the two halves),
-// the same value on every lane.
+// Sum over the wavefront in a fixed order, the same value on every lane.
 __device__ __forceinline__ double wave_sum(double v) {
-    v += swz_xor<1>(v);
-    v += swz_xor<2>(v);
-    v += swz_xor<4>(v);
-    v += swz_xor<8>(v);
-    v += swz_xor<16>(v);
-    return lane_value(v, 0) + lane_value(v, 32);
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    v += dpp_f64<kDppHalfMirror>(v);
+    v += dpp_f64<kDppMirror>(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 // A_ik = |y_i - y_k|^3 (the cubic polyharmonic spline between two support nodes).
@@ -153,42 +154,94 @@ __device__ __forceinline__ double phs3(const double *y, int i, int k) {
     return (r * r) * r;
 }
 
-// P_ij = monomial j at support node i.
-template <int DIM>
-__device__ __forceinline__ double monomial(const double *y, const int8_t *ex, int i, int j) {
-    double p = 1.0;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a)
-        for (int e = 0; e < ex[3 * j + a]; ++e) p *= y[3 * i + a];
-    return p;
+// A double in LDS (address space 3): volatile stores through it stay single
+// ds_write_b64 (not paired, so no register copies for the pair's operands).
+typedef __attribute__((address_space(3))) double lds_f64;
+
+// An offset the compiler cannot fold into later address arithmetic: the LDS
+// base of a row is computed once, and the static offsets of its elements fit
+// the instructions' offset fields.
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
 }
 
-// x[j] -= f * src[j] for j0 <= j < j1 (compile-time bounds once unrolled):
-// the reads in chunks of 4, each chunk's reads issued before the previous
-// chunk's products, and scheduling fences between chunks, so that only two
-// chunks of operands are in registers next to the row.
-template <int B>
+// x[j] -= f * src[j] for j0 <= j < j1 (compile-time bounds once unrolled;
+// src 16-byte aligned and readable up to the even index past j1 - 1).  The
+// reads are 16-byte pairs in chunks of two pairs, D chunks ahead of the
+// products, into D + 1 rotating slots, with scheduling fences between chunks
+// so the compiler neither hoists every read of the row (registers) nor sinks
+// them next to their use (LDS latency).
+template <int B, int D>
 __device__ __forceinline__ void row_axpy(double (&x)[B], const double *src, double f, int j0, int j1) {
-    constexpr int CH = 4;
-    double cur[CH], nxt[CH];
+    constexpr int CP = 2, NS = D + 1, NC = (B / 2 + CP - 1) / CP + 1;
+    const double2 *s2 = reinterpret_cast<const double2 *>(src);
+    const int p0 = j0 / 2, p1 = (j1 + 1) / 2;
+    double2 buf[NS][CP];
 #pragma unroll
-    for (int q = 0; q < CH; ++q) cur[q] = j0 + q < j1 ? src[j0 + q] : 0.0;
+    for (int c = 0; c < D; ++c)
 #pragma unroll
-    for (int c = 0; c < B; c += CH) {
-        const int cj = j0 + c;
-        if (cj < j1) {
+        for (int q = 0; q < CP; ++q) {
+            const int pp = p0 + c * CP + q;
+            buf[c][q] = pp < p1 ? s2[pp] : double2{0.0, 0.0};
+        }
 #pragma unroll
-            for (int q = 0; q < CH; ++q) nxt[q] = cj + CH + q < j1 ? src[cj + CH + q] : 0.0;
+    for (int c = 0; c < NC; ++c) {
+        const int cp = p0 + c * CP;
+        if (cp < p1) {
+#pragma unroll
+            for (int q = 0; q < CP; ++q) {
+                const int pp = cp + D * CP + q;
+                if (pp < p1) buf[(c + D) % NS][q] = s2[pp];
+            }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int q = 0; q < CH; ++q)
-                if (cj + q < j1) x[cj + q] = fma(-f, cur[q], x[cj + q]);
+            for (int q = 0; q < CP; ++q) {
+                const int j = 2 * (cp + q);
+                const double2 v = buf[c % NS][q];
+                if (j >= j0 && j < j1 && j < B) x[j] = fma(-f, v.x, x[j]);
+                if (j + 1 >= j0 && j + 1 < j1 && j + 1 < B) x[j + 1] = fma(-f, v.y, x[j + 1]);
+            }
             __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int q = 0; q < CH; ++q) cur[q] = nxt[q];
         }
     }
 }
+
+// Exponents of the first 96 monomials in the graded order of make_exponents
+// (degree, then the x exponent descending, then the y exponent descending),
+// as a compile-time table: indexed from fully unrolled loops, every lookup
+// folds to a constant.
+struct MonoExp {
+    signed char e[96][3];
+};
+
+template <int DIM>
+constexpr MonoExp make_mono_exp() {
+    MonoExp t{};
+    int c = 0;
+    for (int deg = 0; c < 96; ++deg) {
+        if (DIM == 1) {
+            t.e[c][0] = (signed char)deg;
+            ++c;
+        } else if (DIM == 2) {
+            for (int e0 = deg; e0 >= 0 && c < 96; --e0, ++c) {
+                t.e[c][0] = (signed char)e0;
+                t.e[c][1] = (signed char)(deg - e0);
+            }
+        } else {
+            for (int e0 = deg; e0 >= 0; --e0)
+                for (int e1 = deg - e0; e1 >= 0 && c < 96; --e1, ++c) {
+                    t.e[c][0] = (signed char)e0;
+                    t.e[c][1] = (signed char)e1;
+                    t.e[c][2] = (signed char)(deg - e0 - e1);
+                }
+        }
+    }
+    return t;
+}
+
+template <int DIM>
+constexpr MonoExp kMonoExp = make_mono_exp<DIM>();
 
 template <int DIM, int B>
 __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, double *lds) {
@@ -205,7 +258,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     const LuLayout L = lu_layout(n, M, B);
     double *y = lds + L.y, *b1 = lds + L.b1, *b2 = lds + L.b2, *vec = lds + L.vec, *misc = lds + L.misc;
     int *ipiv = (int *)(lds + L.ints), *inp = ipiv + M;
-    double *rhs = vec, *yv = vec + B, *zv = vec + 2 * B, *ldiag = vec + 3 * B;
+    double *rhs = vec, *yv = vec + B, *zv = vec + 2 * B, *ldiag = vec + 3 * B;  // ldiag: 1 / L[k][k]
     double *red = misc;                       // reductions (kLW doubles)
     double *sc = misc + 8;                    // s
     int *wcnt = (int *)(misc + 12);           // non-pivot rows per wavefront
@@ -235,76 +288,85 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     {
     double x[B];
     double pmax = 0.0;
+    {
+        // powers of the row's coordinates, then products in the graded order
+        const int rr = row < n ? row : 0;
+        constexpr int E = 6;  // m <= 6; entries past M are discarded
+        double pw[DIM][E + 1];
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
-        double v = 0.0;
-        if (j < M) {
-            if (row < n) v = monomial<DIM>(y, ex, row, j);
-            else if (row == n) v = b2[j];
+        for (int a = 0; a < DIM; ++a) {
+            const double ya = y[3 * rr + a];
+            pw[a][0] = 1.0;
+#pragma unroll
+            for (int e = 1; e <= E; ++e) pw[a][e] = pw[a][e - 1] * ya;
         }
-        x[j] = v;
-        if (row < n) pmax = fmax(pmax, fabs(v));
-        if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            double mj = pw[0][min((int)kMonoExp<DIM>.e[j][0], E)];
+#pragma unroll
+            for (int a = 1; a < DIM; ++a) mj *= pw[a][min((int)kMonoExp<DIM>.e[j][a], E)];
+            const double v = j < M ? (row < n ? mj : (row == n ? b2[j] : 0.0)) : 0.0;
+            x[j] = v;
+            pmax = fmax(pmax, row < n ? fabs(v) : 0.0);
+        }
     }
     const double tinyP = group_max(pmax, t, kLT, red) * 0x1p-45;
     bad = !(s > 0.0);
     bool isfree = row < n;
     int mystep = -1;
-    constexpr int SL = B + 2;  // candidate slot: |pivot|, row, row entries 0..B-1
-    {
-        const double v = isfree ? fabs(x[0]) : -1.0;
+    // candidates, double-buffered: per wavefront a header (|pivot|, row,
+    // pivot) and the row's entries past the pivot column
+    double *hdr = xreg;                    // [2][kLW][4]
+    double *slots = xreg + 8 * kLW;        // [2][kLW][B]
+    auto post = [&](int k1, double v) __attribute__((always_inline)) {  // candidate for column k1: |x[k1]| or -1
         const double wm = wave_max(v);
         const unsigned long long bl = __ballot(v == wm);
         if (lane == __ffsll((unsigned long long)bl) - 1) {
-            double *sl = xreg + wave * SL;
-            sl[0] = wm;
-            sl[1] = (double)row;
+            // one lane writes: single stores straight from the row registers
+            volatile lds_f64 *h = (volatile lds_f64 *)(hdr + ((k1 & 1) * kLW + wave) * 4);
+            h[0] = wm;
+            h[1] = (double)row;
+            volatile lds_f64 *sl = (volatile lds_f64 *)(slots + opaque(((k1 & 1) * kLW + wave) * B));
 #pragma unroll
-            for (int j = 0; j < B; ++j) sl[2 + j] = x[j];
+            for (int j = 0; j < B; ++j) {
+                if (j == k1) h[2] = x[j];
+                if (j > k1) sl[j] = x[j];
+            }
         }
-    }
+    };
+    post(0, isfree ? fabs(x[0]) : -1.0);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < B; ++k) {
         if (k < M && !bad) {
-            const double *sb = xreg + (k & 1) * kLW * SL;
-            double best = sb[0];
-            int bw = 0;
+            const double *hb = hdr + (k & 1) * kLW * 4;
+            double best = hb[0], pv = hb[2];
+            int bw = 0, prow = (int)hb[1];
 #pragma unroll
             for (int w = 1; w < kLW; ++w) {
-                const double v = sb[w * SL];
+                const double v = hb[4 * w];
                 if (v > best) {
                     best = v;
                     bw = w;
+                    pv = hb[4 * w + 2];
+                    prow = (int)hb[4 * w + 1];
                 }
             }
             if (!(best > tinyP)) {
                 bad = true;  // uniform: every thread read the same candidates
             } else {
-                const double *u = sb + bw * SL;
-                const int prow = (int)u[1];
-                const double pv = u[2 + k];
+                const double *u = slots + opaque(((k & 1) * kLW + bw) * B);
+                const double rpv = 1.0 / pv;
                 if (row == prow) {
                     isfree = false;
                     mystep = k;
                 }
                 if (isfree || row == n) {
-                    const double l = x[k] / pv;
+                    const double l = x[k] * rpv;
                     x[k] = l;
-                    row_axpy<B>(x, u + 2, l, k + 1, B);
+                    row_axpy<B, 4>(x, u, l, k + 1, B);
                 }
-                if (k + 1 < M) {
-                    const double v = isfree ? fabs(x[k + 1]) : -1.0;
-                    const double wm = wave_max(v);
-                    const unsigned long long bl = __ballot(v == wm);
-                    if (lane == __ffsll((unsigned long long)bl) - 1) {
-                        double *sl = xreg + (((k + 1) & 1) * kLW + wave) * SL;
-                        sl[0] = wm;
-                        sl[1] = (double)row;
-#pragma unroll
-                        for (int j = k + 1; j < B; ++j) sl[2 + j] = x[j];
-                    }
-                }
+                if (k + 1 < M) post(k + 1, isfree ? fabs(x[k + 1]) : -1.0);
                 __syncthreads();
             }
         }
@@ -332,7 +394,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
         if (wave * 64 <= n) {
 #pragma unroll
             for (int i = B - 1; i >= 1; --i) {
-                if (i < M) row_axpy<B>(x, xreg + l1_off(i), x[i], 0, i);
+                if (i < M) row_axpy<B, 4>(x, xreg + opaque(l1_off(i)), x[i], 0, i);
             }
         }
         __syncthreads();  // L1 read before [X v1] overwrites it
@@ -493,21 +555,22 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
 #pragma unroll
     for (int k = 0; k < B; ++k) {
         if (k < K && !bad) {
-            double *cbk = colb + (k & 1) * (B + 2);
+            double *cbk = colb + opaque((k & 1) * (B + 2));
             if (crow && ci >= k) cbk[ci] = x[k];
             __syncthreads();
             const double d = cbk[k];
             if (!(d > tinyC)) {
                 bad = true;  // uniform
             } else {
-                const double lkk = sqrt(d);
-                if (t == 0) ldiag[k] = lkk;
+                const double rd = 1.0 / d;
+                const double rl = sqrt(rd);  // 1 / L[k][k]
+                if (t == 0) ldiag[k] = rl;
                 if (crow && ci > k) {
-                    const double f = x[k] / d;
+                    const double f = x[k] * rd;
                     // columns up to B - 1: those past K hold no row entries
                     // (never read by rows 0..K), so the update stays static
-                    row_axpy<B>(x, cbk, f, k + 1, B);
-                    x[k] = x[k] / lkk;  // L[ci][k] (row K: (L^{-1} r)_k)
+                    row_axpy<B, 2>(x, cbk, f, k + 1, B);
+                    x[k] = x[k] * rl;  // L[ci][k] (row K: (L^{-1} r)_k)
                 }
             }
         }
@@ -528,7 +591,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
                 p = wave_sum(p);
                 if (lane == 0 && wave < 2) part[(k & 1) * 2 + wave] = p;
                 __syncthreads();
-                if (ci == k) zi = (yv[k] - (part[(k & 1) * 2] + part[(k & 1) * 2 + 1])) / ldiag[k];
+                if (ci == k) zi = (yv[k] - (part[(k & 1) * 2] + part[(k & 1) * 2 + 1])) * ldiag[k];
             }
         }
         if (ci < K) zv[ci] = zi;
