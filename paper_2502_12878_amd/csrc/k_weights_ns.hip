@@ -9,13 +9,12 @@ RBF_NS_SIZES(RBF_NS_DECL)
 
 namespace {
 
-// register-array sizes compiled per dimension (2D: m <= 6 gives M <= 28)
-constexpr int kBuckets2[] = {16, 24, 40, 64};
-constexpr int kBuckets3[] = {24, 40, 64, 88};
+// A compiled size as one key: 1000 * MB + KB.
+constexpr int ns_key(int mb, int kb) { return 1000 * mb + kb; }
 
-const void *ns_kernel(int dim, int b) {
-#define RBF_NS_K(D, BB) \
-    if (dim == D && b == BB) return ns_kernel_##D##_##BB();
+const void *ns_kernel(int dim, int key) {
+#define RBF_NS_K(D, MBB, KBB) \
+    if (dim == D && key == ns_key(MBB, KBB)) return ns_kernel_##D##_##MBB##_##KBB();
     RBF_NS_SIZES(RBF_NS_K)
 #undef RBF_NS_K
     return nullptr;
@@ -23,18 +22,21 @@ const void *ns_kernel(int dim, int b) {
 
 }  // namespace
 
-// Register-array size for (n, M): the smallest compiled bucket holding M and
-// K + 1, with n + 1 rows on the workgroup's lanes; 0 if none (1D systems are
-// small enough for the elimination paths).
+// Compiled size for (n, M): the first (in the order of RBF_NS_SIZES) whose
+// LU rows hold M entries and Cholesky rows K + 1, as the key 1000 MB + KB,
+// with n + 1 rows on the workgroup's lanes; 0 if none (1D systems are small
+// enough for the elimination paths).
 int ns_bucket(int dim, int n, int M) {
     const int K = n - M;
-    if (K < 1 || M < 2 || n + 1 > kLT || (dim != 2 && dim != 3)) return 0;
-    for (int b : (dim == 2 ? kBuckets2 : kBuckets3))
-        if (M <= b && K + 1 <= b) return b;
+    if (K < 1 || M < 2 || n + 1 > kLT) return 0;
+#define RBF_NS_B(D, MBB, KBB) \
+    if (dim == D && M <= MBB && K + 1 <= KBB) return ns_key(MBB, KBB);
+    RBF_NS_SIZES(RBF_NS_B)
+#undef RBF_NS_B
     return 0;
 }
 
-int ns_lds_doubles(int n, int M, int bucket) { return lu_layout(n, M, bucket).total; }
+int ns_lds_doubles(int n, int M, int bucket) { return lu_layout(n, M, bucket / 1000, bucket % 1000).total; }
 
 bool ns_fits(int dim, int n, int M, size_t lds_limit) {
     const int b = ns_bucket(dim, n, M);
@@ -63,10 +65,10 @@ hipError_t launch_weights_ns(hipStream_t s, int dim, int bucket, int64_t N, cons
     if (grid <= 0 || !kern) return hipErrorInvalidConfiguration;
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
-#define RBF_NS_L(D, BB)                                                                                       \
-    if (dim == D && bucket == BB)                                                                            \
-        return ns_launch_##D##_##BB(s, grid, lds_bytes, N, xyz, sten, nrow, n_max, rows, mrow, type, normals, \
-                                    w_out, status, items, nitems, counter);
+#define RBF_NS_L(D, MBB, KBB)                                                                                  \
+    if (dim == D && bucket == ns_key(MBB, KBB))                                                                \
+        return ns_launch_##D##_##MBB##_##KBB(s, grid, lds_bytes, N, xyz, sten, nrow, n_max, rows, mrow, type,     \
+                                             normals, w_out, status, items, nitems, counter);
     RBF_NS_SIZES(RBF_NS_L)
 #undef RBF_NS_L
     return hipErrorInvalidConfiguration;

@@ -1,9 +1,9 @@
-// Compiled sizes of the null-space weight kernel: 3D with 24-entry row arrays, 3D with 40-entry row arrays.
+// Compiled sizes of the null-space weight kernel (dimension, LU row entries, Cholesky row entries): (3, 20, 32), (3, 36, 40).
 #include "weights_ns_impl.h"
 
 namespace rbf {
 
-RBF_NS_INSTANCE(3, 24)
-RBF_NS_INSTANCE(3, 40)
+RBF_NS_INSTANCE(3, 20, 32)
+RBF_NS_INSTANCE(3, 36, 40)
 
 }  // namespace rbf

@@ -1,8 +1,8 @@
-// Compiled sizes of the null-space weight kernel: 3D with 64-entry row arrays.
+// Compiled sizes of the null-space weight kernel (dimension, LU row entries, Cholesky row entries): (3, 56, 64).
 #include "weights_ns_impl.h"
 
 namespace rbf {
 
-RBF_NS_INSTANCE(3, 64)
+RBF_NS_INSTANCE(3, 56, 64)
 
 }  // namespace rbf

@@ -65,7 +65,7 @@ struct LuLayout {
     int y, b1, b2, ints, vec, misc, xreg, treg, total;
 };
 
-__host__ __device__ inline LuLayout lu_layout(int n, int M, int B) {
+__host__ __device__ inline LuLayout lu_layout(int n, int M, int MB, int KB) {
     LuLayout L{};
     L.n = n;
     L.M = M;
@@ -85,19 +85,19 @@ __host__ __device__ inline LuLayout lu_layout(int n, int M, int B) {
     L.ints = o;                // int32 pivot rows [M], non-pivot rows [K]
     o += (n + 1) / 2 + 1;
     o += o & 1;
-    L.vec = o;                 // rhs [B], L^{-1} r [B], z [B], 1 / diag L [B]
-    o += 4 * B;
+    L.vec = o;                 // rhs [KB], L^{-1} r [KB], z [KB], 1 / diag L [KB]
+    o += 4 * KB;
     L.misc = o;
     o += 64;
     L.xreg = o;                // LU candidate rows, then L1, then [X v1]
-    int xr = 8 * kLW + 2 * kLW * B;
+    int xr = 8 * kLW + 2 * kLW * MB;
     if (l1_off(M) + 2 > xr) xr = l1_off(M) + 2;
     if (M * L.ldx > xr) xr = M * L.ldx;
     o += xr + (xr & 1);
     L.treg = o;                // block of A, then C_aug staging, then Cholesky columns
     int tr = 16 * L.lda;
     if (16 * L.ldst > tr) tr = 16 * L.ldst;
-    if (2 * (B + 2) > tr) tr = 2 * (B + 2);
+    if (2 * (KB + 2) > tr) tr = 2 * (KB + 2);
     o += tr + (tr & 1);
     L.total = o;
     return L;
@@ -243,7 +243,7 @@ constexpr MonoExp make_mono_exp() {
 template <int DIM>
 constexpr MonoExp kMonoExp = make_mono_exp<DIM>();
 
-template <int DIM, int B>
+template <int DIM, int MB, int KB>
 __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, double *lds) {
     const int t = threadIdx.x;
     const int lane = t & 63;
@@ -255,10 +255,10 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     const int M = num_monomials(DIM, m);
     const int K = n - M;
     const int S = n + M;
-    const LuLayout L = lu_layout(n, M, B);
+    const LuLayout L = lu_layout(n, M, MB, KB);
     double *y = lds + L.y, *b1 = lds + L.b1, *b2 = lds + L.b2, *vec = lds + L.vec, *misc = lds + L.misc;
     int *ipiv = (int *)(lds + L.ints), *inp = ipiv + M;
-    double *rhs = vec, *yv = vec + B, *zv = vec + 2 * B, *ldiag = vec + 3 * B;  // ldiag: 1 / L[k][k]
+    double *rhs = vec, *yv = vec + KB, *zv = vec + 2 * KB, *ldiag = vec + 3 * KB;  // ldiag: 1 / L[k][k]
     double *red = misc;                       // reductions (kLW doubles)
     double *sc = misc + 8;                    // s
     int *wcnt = (int *)(misc + 12);           // non-pivot rows per wavefront
@@ -286,7 +286,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     int rank = -1;
     bool bad = false;
     {
-    double x[B];
+    double x[MB];
     double pmax = 0.0;
     {
         // powers of the row's coordinates, then products in the graded order
@@ -301,7 +301,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
             for (int e = 1; e <= E; ++e) pw[a][e] = pw[a][e - 1] * ya;
         }
 #pragma unroll
-        for (int j = 0; j < B; ++j) {
+        for (int j = 0; j < MB; ++j) {
             double mj = pw[0][min((int)kMonoExp<DIM>.e[j][0], E)];
 #pragma unroll
             for (int a = 1; a < DIM; ++a) mj *= pw[a][min((int)kMonoExp<DIM>.e[j][a], E)];
@@ -317,7 +317,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     // candidates, double-buffered: per wavefront a header (|pivot|, row,
     // pivot) and the row's entries past the pivot column
     double *hdr = xreg;                    // [2][kLW][4]
-    double *slots = xreg + 8 * kLW;        // [2][kLW][B]
+    double *slots = xreg + 8 * kLW;        // [2][kLW][MB]
     auto post = [&](int k1, double v) __attribute__((always_inline)) {  // candidate for column k1: |x[k1]| or -1
         const double wm = wave_max(v);
         const unsigned long long bl = __ballot(v == wm);
@@ -326,9 +326,9 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
             volatile lds_f64 *h = (volatile lds_f64 *)(hdr + ((k1 & 1) * kLW + wave) * 4);
             h[0] = wm;
             h[1] = (double)row;
-            volatile lds_f64 *sl = (volatile lds_f64 *)(slots + opaque(((k1 & 1) * kLW + wave) * B));
+            volatile lds_f64 *sl = (volatile lds_f64 *)(slots + opaque(((k1 & 1) * kLW + wave) * MB));
 #pragma unroll
-            for (int j = 0; j < B; ++j) {
+            for (int j = 0; j < MB; ++j) {
                 if (j == k1) h[2] = x[j];
                 if (j > k1) sl[j] = x[j];
             }
@@ -337,7 +337,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     post(0, isfree ? fabs(x[0]) : -1.0);
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < B; ++k) {
+    for (int k = 0; k < MB; ++k) {
         if (k < M && !bad) {
             const double *hb = hdr + (k & 1) * kLW * 4;
             double best = hb[0], pv = hb[2];
@@ -355,7 +355,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
             if (!(best > tinyP)) {
                 bad = true;  // uniform: every thread read the same candidates
             } else {
-                const double *u = slots + opaque(((k & 1) * kLW + bw) * B);
+                const double *u = slots + opaque(((k & 1) * kLW + bw) * MB);
                 const double rpv = 1.0 / pv;
                 if (row == prow) {
                     isfree = false;
@@ -364,7 +364,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
                 if (isfree || row == n) {
                     const double l = x[k] * rpv;
                     x[k] = l;
-                    row_axpy<B, 4>(x, u, l, k + 1, B);
+                    row_axpy<MB, 4>(x, u, l, k + 1, MB);
                 }
                 if (k + 1 < M) post(k + 1, isfree ? fabs(x[k + 1]) : -1.0);
                 __syncthreads();
@@ -378,7 +378,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
             ipiv[mystep] = row;
             double *lr = xreg + l1_off(mystep);
 #pragma unroll
-            for (int j = 0; j + 1 < B; ++j)
+            for (int j = 0; j + 1 < MB; ++j)
                 if (j < mystep) lr[j] = x[j];
         }
         const unsigned long long bl = __ballot(isfree);
@@ -393,18 +393,18 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
         // ---- 3. L1^T xi = multipliers (rows of L1 from LDS, right-looking)
         if (wave * 64 <= n) {
 #pragma unroll
-            for (int i = B - 1; i >= 1; --i) {
-                if (i < M) row_axpy<B, 4>(x, xreg + opaque(l1_off(i)), x[i], 0, i);
+            for (int i = MB - 1; i >= 1; --i) {
+                if (i < M) row_axpy<MB, 4>(x, xreg + opaque(l1_off(i)), x[i], 0, i);
             }
         }
         __syncthreads();  // L1 read before [X v1] overwrites it
         if (isfree) {
 #pragma unroll
-            for (int j = 0; j < B; ++j)
+            for (int j = 0; j < MB; ++j)
                 if (j < M) Xs[j * ldx + rank] = -x[j];
         } else if (row == n) {
 #pragma unroll
-            for (int j = 0; j < B; ++j)
+            for (int j = 0; j < MB; ++j)
                 if (j < M) Xs[j * ldx + K] = x[j];
         }
         __syncthreads();
@@ -424,9 +424,9 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
 #pragma unroll
     for (int d = 0; d < 2; ++d) acc1[d] = f64x4{0.0, 0.0, 0.0, 0.0};
     if (!bad) {
-        double xr0[B / 4], xr1[B / 4];
+        double xr0[MB / 4], xr1[MB / 4];
 #pragma unroll
-        for (int q = 0; q < B / 4; ++q) {
+        for (int q = 0; q < MB / 4; ++q) {
             const int j = 4 * q + lq;
             const int c0 = 16 * cb0 + l16, c1 = 16 * cb1 + l16;
             xr0[q] = (cb0 >= 0 && j < M && c0 <= K) ? Xs[j * ldx + c0] : 0.0;
@@ -447,53 +447,68 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
                     at[i * lda + j] = (rv && j < M) ? phs3<DIM>(y, ri, ipiv[j]) : 0.0;
             }
             __syncthreads();
+            // T = A[block, pivots] [X v1] + A[block, non-pivots] [I 0] for both
+            // column blocks, the identity part as the initial value; the two
+            // accumulation chains interleaved, one A-block read for both
+            const int cc0 = 16 * cb0 + l16, cc1 = 16 * cb1 + l16;
+            f64x4 T0 = {0.0, 0.0, 0.0, 0.0}, T1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int cb = h == 0 ? cb0 : cb1;
-                if (cb >= 0) {
-                    // identity part A[block, non-pivots] [I 0] as the initial value
-                    f64x4 T;
-                    const int cc = 16 * cb + l16;
+            for (int r = 0; r < 4; ++r) {
+                const int i = lq + 4 * r;
+                const bool rv = r0 + i < rlim;
+                const int ri = rv ? rowpos[r0 + i] : 0;
+                if (cb0 >= 0) T0[r] = (rv && cc0 < K) ? phs3<DIM>(y, ri, inp[cc0]) : 0.0;
+                if (cb1 >= 0) T1[r] = (rv && cc1 < K) ? phs3<DIM>(y, ri, inp[cc1]) : 0.0;
+            }
+            const double *ar = at + l16 * lda + lq;
+            if (cb1 >= 0) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = lq + 4 * r;
-                        T[r] = (r0 + i < rlim && cc < K) ? phs3<DIM>(y, rowpos[r0 + i], inp[cc]) : 0.0;
+                for (int q = 0; q < MB / 4; ++q)
+                    if (4 * q < M4) {
+                        const double av = ar[4 * q];
+                        T0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xr0[q], T0, 0, 0, 0);
+                        T1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xr1[q], T1, 0, 0, 0);
                     }
-                    const double *ar = at + l16 * lda + lq;
+            } else if (cb0 >= 0) {
 #pragma unroll
-                    for (int q = 0; q < B / 4; ++q)
-                        if (4 * q < M4)
-                            T = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[4 * q], h == 0 ? xr0[q] : xr1[q], T, 0, 0, 0);
-                    if (pivb) {
-                        // C_aug[a, cb] += [X v1]^T[a-block, block rows] T
+                for (int q = 0; q < MB / 4; ++q)
+                    if (4 * q < M4) T0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[4 * q], xr0[q], T0, 0, 0, 0);
+            }
+            if (pivb) {
+                // C_aug[a, cb] += [X v1]^T[a-block, block rows] T, the tiles'
+                // chains interleaved
 #pragma unroll
-                        for (int d = 0; d < 6; ++d) {
-                            const int a = cb + d;
-                            if (a < nJ && (h == 0 || d < 2)) {
-                                f64x4 acc = h == 0 ? acc0[d] : acc1[d < 2 ? d : 0];
-                                const int ca = 16 * a + l16;
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    const int j = r0 + 4 * s4 + lq;
+                    const bool jv = j < M;
 #pragma unroll
-                                for (int s4 = 0; s4 < 4; ++s4) {
-                                    const int j = r0 + 4 * s4 + lq;
-                                    const double xa = (j < M && ca <= K) ? Xs[j * ldx + ca] : 0.0;
-                                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, T[s4], acc, 0, 0, 0);
-                                }
-                                if (h == 0) acc0[d] = acc;
-                                else acc1[d < 2 ? d : 0] = acc;
-                            }
+                    for (int d = 0; d < 6; ++d) {
+                        const int a = cb0 + d;
+                        if (cb0 >= 0 && a < nJ) {
+                            const int ca = 16 * a + l16;
+                            const double xa = (jv && ca <= K) ? Xs[j * ldx + ca] : 0.0;
+                            acc0[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, T0[s4], acc0[d], 0, 0, 0);
                         }
-                    } else {
-                        // rows M + r0 .. : C_aug[r0 / 16, cb] += T (same fragment layout)
-                        const int a = r0 / 16;
+                    }
 #pragma unroll
-                        for (int d = 0; d < 6; ++d) {
-                            if (a == cb + d && (h == 0 || d < 2)) {
-                                if (h == 0) acc0[d] += T;
-                                else acc1[d < 2 ? d : 0] += T;
-                            }
+                    for (int d = 0; d < 2; ++d) {
+                        const int a = cb1 + d;
+                        if (cb1 >= 0 && a < nJ) {
+                            const int ca = 16 * a + l16;
+                            const double xa = (jv && ca <= K) ? Xs[j * ldx + ca] : 0.0;
+                            acc1[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, T1[s4], acc1[d], 0, 0, 0);
                         }
                     }
                 }
+            } else {
+                // rows M + r0 .. : C_aug[r0 / 16, cb] += T (same fragment layout)
+                const int a = r0 / 16;
+#pragma unroll
+                for (int d = 0; d < 6; ++d)
+                    if (cb0 >= 0 && a == cb0 + d) acc0[d] += T0;
+#pragma unroll
+                for (int d = 0; d < 2; ++d)
+                    if (cb1 >= 0 && a == cb1 + d) acc1[d] += T1;
             }
             __syncthreads();
         }
@@ -512,9 +527,9 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
         rhs[t] = (a0 + a1) + b1[inp[t]];
     }
     // lower tiles of C_aug to one row per lane (rows 0..K), by row blocks
-    double x[B];
+    double x[KB];
 #pragma unroll
-    for (int j = 0; j < B; ++j) x[j] = 0.0;
+    for (int j = 0; j < KB; ++j) x[j] = 0.0;
     double dmax = 0.0;
     if (!bad) {
         double *st = treg;
@@ -538,7 +553,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
             if (t >= 16 * a && t < 16 * a + 16 && t <= K) {
                 const double *sr = st + (t - 16 * a) * ldst;
 #pragma unroll
-                for (int j = 0; j < B; ++j) x[j] = j <= t ? sr[j] : 0.0;
+                for (int j = 0; j < KB; ++j) x[j] = j <= t ? sr[j] : 0.0;
                 if (t < K) dmax = sr[t];
             }
             __syncthreads();
@@ -549,13 +564,13 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     const bool crow = ci <= K;
     if (!bad && ci == K) {
 #pragma unroll
-        for (int j = 0; j < B; ++j) x[j] = j < K ? rhs[j] - x[j] : 0.0;
+        for (int j = 0; j < KB; ++j) x[j] = j < K ? rhs[j] - x[j] : 0.0;
     }
-    double *colb = treg;  // column k of the updated matrix, double-buffered [2][B + 2]
+    double *colb = treg;  // column k of the updated matrix, double-buffered [2][KB + 2]
 #pragma unroll
-    for (int k = 0; k < B; ++k) {
+    for (int k = 0; k < KB; ++k) {
         if (k < K && !bad) {
-            double *cbk = colb + opaque((k & 1) * (B + 2));
+            double *cbk = colb + opaque((k & 1) * (KB + 2));
             if (crow && ci >= k) cbk[ci] = x[k];
             __syncthreads();
             const double d = cbk[k];
@@ -567,9 +582,9 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
                 if (t == 0) ldiag[k] = rl;
                 if (crow && ci > k) {
                     const double f = x[k] * rd;
-                    // columns up to B - 1: those past K hold no row entries
+                    // columns up to KB - 1: those past K hold no row entries
                     // (never read by rows 0..K), so the update stays static
-                    row_axpy<B, 2>(x, cbk, f, k + 1, B);
+                    row_axpy<KB, 2>(x, cbk, f, k + 1, KB);
                     x[k] = x[k] * rl;  // L[ci][k] (row K: (L^{-1} r)_k)
                 }
             }
@@ -578,14 +593,14 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     if (!bad) {
         if (ci == K) {
 #pragma unroll
-            for (int j = 0; j < B; ++j)
+            for (int j = 0; j < KB; ++j)
                 if (j < K) yv[j] = x[j];
         }
         __syncthreads();
         // L^T z = L^{-1} r: z_k from the column-k products of the rows below
         double zi = 0.0;
 #pragma unroll
-        for (int k = B - 1; k >= 0; --k) {
+        for (int k = KB - 1; k >= 0; --k) {
             if (k < K) {
                 double p = (ci > k && ci < K) ? x[k] * zi : 0.0;
                 p = wave_sum(p);
@@ -621,7 +636,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     __syncthreads();
 }
 
-template <int DIM, int B>
+template <int DIM, int MB, int KB>
 __global__ __launch_bounds__(kLT) __attribute__((amdgpu_waves_per_eu(2))) void k_weights_ns(
     WCtx cx, const Item *__restrict__ items, int64_t nitems, int32_t *counter) {
     extern __shared__ __align__(16) double lds_ns[];
@@ -632,31 +647,37 @@ __global__ __launch_bounds__(kLT) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int64_t q = s_item;
         __syncthreads();
         if (q >= nitems) return;
-        solve_lu_item<DIM, B>(cx, items[q], lds_ns);
+        solve_lu_item<DIM, MB, KB>(cx, items[q], lds_ns);
     }
 }
 
 }  // namespace
 
-// One compiled size: kernel handle and launch (defined by RBF_NS_INSTANCE in
-// the instance files).
-#define RBF_NS_DECL(D, BB)                                                                                    \
-    const void *ns_kernel_##D##_##BB();                                                                       \
-    hipError_t ns_launch_##D##_##BB(hipStream_t s, int grid, size_t lds_bytes, int64_t N, const double *xyz,     \
-                                    const int32_t *sten, const int16_t *nrow, int32_t n_max, const int32_t *rows, \
-                                    const int8_t *mrow, const int8_t *type, const double *normals, double *w_out,  \
-                                    DevStatus *status, const void *items, int64_t nitems, int32_t *counter);
-#define RBF_NS_INSTANCE(D, BB)                                                                                \
-    const void *ns_kernel_##D##_##BB() { return (const void *)k_weights_ns<D, BB>; }                          \
-    hipError_t ns_launch_##D##_##BB(hipStream_t s, int grid, size_t lds_bytes, int64_t N, const double *xyz,     \
-                                    const int32_t *sten, const int16_t *nrow, int32_t n_max, const int32_t *rows, \
-                                    const int8_t *mrow, const int8_t *type, const double *normals, double *w_out,  \
-                                    DevStatus *status, const void *items, int64_t nitems, int32_t *counter) {      \
-        WCtx cx{D, N, xyz, sten, nrow, n_max, rows, mrow, w_out, type, normals, nullptr, 0, 0, status};          \
-        hipLaunchKernelGGL((k_weights_ns<D, BB>), dim3(grid), dim3(kLT), lds_bytes, s, cx, (const Item *)items, \
-                           nitems, counter);                                                                     \
+// One compiled size (row arrays of MB entries for the LU, KB for the
+// Cholesky): kernel handle and launch, defined by RBF_NS_INSTANCE in the
+// instance files.
+#define RBF_NS_DECL(D, MBB, KBB)                                                                                \
+    const void *ns_kernel_##D##_##MBB##_##KBB();                                                                \
+    hipError_t ns_launch_##D##_##MBB##_##KBB(hipStream_t s, int grid, size_t lds_bytes, int64_t N,                \
+                                             const double *xyz, const int32_t *sten, const int16_t *nrow,        \
+                                             int32_t n_max, const int32_t *rows, const int8_t *mrow,             \
+                                             const int8_t *type, const double *normals, double *w_out,          \
+                                             DevStatus *status, const void *items, int64_t nitems,              \
+                                             int32_t *counter);
+#define RBF_NS_INSTANCE(D, MBB, KBB)                                                                            \
+    const void *ns_kernel_##D##_##MBB##_##KBB() { return (const void *)k_weights_ns<D, MBB, KBB>; }             \
+    hipError_t ns_launch_##D##_##MBB##_##KBB(hipStream_t s, int grid, size_t lds_bytes, int64_t N,                \
+                                             const double *xyz, const int32_t *sten, const int16_t *nrow,        \
+                                             int32_t n_max, const int32_t *rows, const int8_t *mrow,             \
+                                             const int8_t *type, const double *normals, double *w_out,          \
+                                             DevStatus *status, const void *items, int64_t nitems,              \
+                                             int32_t *counter) {                                                \
+        WCtx cx{D, N, xyz, sten, nrow, n_max, rows, mrow, w_out, type, normals, nullptr, 0, 0, status};           \
+        hipLaunchKernelGGL((k_weights_ns<D, MBB, KBB>), dim3(grid), dim3(kLT), lds_bytes, s, cx,                  \
+                           (const Item *)items, nitems, counter);                                               \
         return hipGetLastError();                                                                                \
     }
-#define RBF_NS_SIZES(X) X(2, 16) X(2, 24) X(2, 40) X(2, 64) X(3, 24) X(3, 40) X(3, 64) X(3, 88)
+// (dimension, MB, KB) of the compiled sizes
+#define RBF_NS_SIZES(X) X(2, 16, 16) X(2, 24, 24) X(2, 40, 40) X(2, 64, 64) X(3, 20, 32) X(3, 36, 40) X(3, 56, 64) X(3, 84, 86)
 
 }  // namespace rbf
