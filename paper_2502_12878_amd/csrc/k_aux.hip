@@ -84,16 +84,38 @@ __global__ void k_sum_partials(const double *__restrict__ p, int n, double *out)
 // The packed rows are internal rows row0 .. row0 + nrows - 1.  With
 // zero_self, a row's own entry keeps its slot with weight 0 and its weight is
 // written to wself[i] instead (the Neumann rows, solved for their own value).
-__global__ void k_pack_ell(int64_t row0, int64_t nrows, int32_t n_max, int32_t kmax, int64_t nslices, int layout,
-                           const int32_t *__restrict__ perm, const int32_t *__restrict__ iperm,
-                           const int32_t *__restrict__ sten, const int16_t *__restrict__ nrow,
-                           const double *__restrict__ w_can, const int64_t *__restrict__ slice_ptr,
-                           const int32_t *__restrict__ slice_len, int32_t *__restrict__ idx, double *__restrict__ w,
-                           float *__restrict__ w32, double *__restrict__ wself, int32_t *__restrict__ foreign) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// The internal column ids of the rows a workgroup touches are staged in LDS
+// first (a 256-thread block spans at most 256 / kmax + 2 rows), so each rank
+// is counted from LDS instead of re-reading the row's ids from memory.
+constexpr int kPackThreads = 256;
+
+__global__ __launch_bounds__(kPackThreads) void k_pack_ell(
+    int64_t row0, int64_t nrows, int32_t n_max, int32_t kmax, int64_t nslices, int layout,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ iperm, const int32_t *__restrict__ sten,
+    const int16_t *__restrict__ nrow, const double *__restrict__ w_can, const int64_t *__restrict__ slice_ptr,
+    const int32_t *__restrict__ slice_len, int32_t *__restrict__ idx, double *__restrict__ w, float *__restrict__ w32,
+    double *__restrict__ wself, int32_t *__restrict__ foreign) {
+    extern __shared__ int32_t pk_cols[];  // [rows of this block][kmax]
+    const int64_t t0 = (int64_t)blockIdx.x * kPackThreads;
+    const int64_t t = t0 + threadIdx.x;
+    const int64_t irow0 = t0 / kmax;
+    const int64_t irows = nslices * kSlice;
+    const int nblk = (int)((t0 + kPackThreads - 1) / kmax - irow0 + 1);
+    // stage: entry q of block row b holds the internal id of support entry q
+    for (int e = threadIdx.x; e < nblk * kmax; e += kPackThreads) {
+        const int b = e / kmax, q = e - b * kmax;
+        const int64_t ii = irow0 + b;
+        int32_t v = -1;
+        if (ii < nrows && ii < irows) {
+            const int64_t r = perm[row0 + ii];
+            if (q < nrow[r]) v = iperm[sten[r * (int64_t)n_max + q]];
+        }
+        pk_cols[e] = v;
+    }
+    __syncthreads();
     const int64_t i = t / kmax;
     const int k = (int)(t - i * kmax);
-    if (i >= nslices * kSlice) return;
+    if (i >= irows) return;
     const int64_t s = i / kSlice;
     const int lane = (int)(i - s * kSlice);
     const int len = slice_len[s];
@@ -109,10 +131,10 @@ __global__ void k_pack_ell(int64_t row0, int64_t nrows, int32_t n_max, int32_t k
         if (k >= n) {
             col = (int32_t)gi;
         } else {
-            const int32_t *row = sten + r * (int64_t)n_max;
-            col = iperm[row[k]];
+            const int32_t *cr = pk_cols + (i - irow0) * kmax;
+            col = cr[k];
             int rank = 0;
-            for (int q = 0; q < n; ++q) rank += (iperm[row[q]] < col) ? 1 : 0;
+            for (int q = 0; q < n; ++q) rank += (cr[q] < col) ? 1 : 0;
             slot = rank;
             wk = w_can[r * (int64_t)n_max + k];
             if (wself && col == gi) {
@@ -264,9 +286,10 @@ hipError_t launch_pack_ell(hipStream_t s, int64_t row0, int64_t nrows, int32_t n
     const int32_t kmax = e.max_len;
     const int64_t total = e.nslices * kSlice * (int64_t)kmax;
     if (!total) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_ell, dim3(grid1d(total, 256)), dim3(256), 0, s, row0, nrows, n_max, kmax, e.nslices,
-                       e.layout, perm, iperm, sten, nrow, w_can, e.slice_ptr, e.slice_len, e.idx, e.w, e.w32, wself,
-                       foreign);
+    const size_t lds = sizeof(int32_t) * (size_t)(kPackThreads / kmax + 2) * kmax;
+    hipLaunchKernelGGL(k_pack_ell, dim3(grid1d(total, kPackThreads)), dim3(kPackThreads), lds, s, row0, nrows, n_max,
+                       kmax, e.nslices, e.layout, perm, iperm, sten, nrow, w_can, e.slice_ptr, e.slice_len, e.idx,
+                       e.w, e.w32, wself, foreign);
     return hipGetLastError();
 }
 

@@ -900,13 +900,24 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
     if (h->N_neu > 0 && !h->normals) return fail(h, RBF_EINVAL, "Neumann nodes need normals (rbf_set_normals)");
     drop_weights(h);
 
-    // group interior rows by (n, m); classes by descending system size
-    std::map<std::pair<int, int>, std::vector<int32_t>> cls;
+    // group interior rows by (n, m) (a counting sort on the key 8 n + m, rows
+    // in ascending id within a class); classes by descending system size
+    constexpr int kKeys = 8 * (kMaxSupport + 1);
+    std::vector<int64_t> kcount(kKeys + 1, 0);
     for (int64_t i = 0; i < N; ++i)
-        if (h->type_h[i] != 1) cls[{h->nrow_h[i], mh[i]}].push_back((int32_t)i);
-    struct Cls { int S, n, m; std::vector<int32_t> *rows; };
+        if (h->type_h[i] != 1) ++kcount[8 * h->nrow_h[i] + mh[i] + 1];
+    for (int k = 0; k < kKeys; ++k) kcount[k + 1] += kcount[k];
+    std::vector<int32_t> grouped((size_t)kcount[kKeys]);
+    {
+        std::vector<int64_t> pos(kcount.begin(), kcount.end() - 1);
+        for (int64_t i = 0; i < N; ++i)
+            if (h->type_h[i] != 1) grouped[(size_t)pos[8 * h->nrow_h[i] + mh[i]]++] = (int32_t)i;
+    }
+    struct Cls { int S, n, m; int64_t begin, end; };
     std::vector<Cls> order;
-    for (auto &kv : cls) order.push_back({kv.first.first + num_monomials(dim, kv.first.second), kv.first.first, kv.first.second, &kv.second});
+    for (int k = 0; k < kKeys; ++k)
+        if (kcount[k + 1] > kcount[k])
+            order.push_back({k / 8 + num_monomials(dim, k % 8), k / 8, k % 8, kcount[k], kcount[k + 1]});
     std::sort(order.begin(), order.end(), [](const Cls &a, const Cls &b) { return a.S > b.S || (a.S == b.S && a.n > b.n); });
     std::vector<int32_t> rows;
     std::vector<int8_t> mrows;
@@ -939,16 +950,14 @@ extern "C" rbf_status rbf_compute_weights(rbf_handle *h, int32_t m_uniform, cons
             mx = std::max(mx, ns_lds_doubles(c.n, c.S - c.n, bucket));
         }
         const int per = kind == 0 ? 4 : 1;
-        const int64_t first = (int64_t)rows.size();
-        for (int32_t r : *c.rows) {
-            rows.push_back(r);
-            mrows.push_back((int8_t)c.m);
-        }
+        const int64_t first = (int64_t)rows.size(), cnt = c.end - c.begin;
+        rows.insert(rows.end(), grouped.begin() + c.begin, grouped.begin() + c.end);
+        mrows.insert(mrows.end(), (size_t)cnt, (int8_t)c.m);
         std::vector<char> &dst = kind == 2 ? ns_launch[bucket].first : items;
-        for (int64_t q = 0; q < (int64_t)c.rows->size(); q += per) {
-            dst.resize(dst.size() + isz);
-            weights_make_item(dst.data() + dst.size() - isz, kind == 2 ? 1 : kind,
-                              (int)std::min<int64_t>(per, c.rows->size() - q), first + q);
+        size_t at = dst.size();
+        dst.resize(at + (size_t)((cnt + per - 1) / per) * isz);
+        for (int64_t q = 0; q < cnt; q += per, at += isz) {
+            weights_make_item(dst.data() + at, kind == 2 ? 1 : kind, (int)std::min<int64_t>(per, cnt - q), first + q);
             if (kind == 2) {
                 ++nitems_ns;
             } else {

@@ -132,15 +132,6 @@ __device__ __forceinline__ double wave_max(double v) {
     return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
 }
 
-// Sum over the wavefront in a fixed order, the same value on every lane.
-__device__ __forceinline__ double wave_sum(double v) {
-    v += dpp_f64<kDppXor1>(v);
-    v += dpp_f64<kDppXor2>(v);
-    v += dpp_f64<kDppHalfMirror>(v);
-    v += dpp_f64<kDppMirror>(v);
-    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
-}
-
 // A_ik = |y_i - y_k|^3 (the cubic polyharmonic spline between two support nodes).
 template <int DIM>
 __device__ __forceinline__ double phs3(const double *y, int i, int k) {
@@ -262,7 +253,6 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     double *red = misc;                       // reductions (kLW doubles)
     double *sc = misc + 8;                    // s
     int *wcnt = (int *)(misc + 12);           // non-pivot rows per wavefront
-    double *part = misc + 16;                 // backward-solve partial sums [2][2]
     int8_t *ex = (int8_t *)(misc + 32);       // monomial exponents (84 x 3 bytes)
     double *xreg = lds + L.xreg, *treg = lds + L.treg;
 
@@ -321,7 +311,10 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     auto post = [&](int k1, double v) __attribute__((always_inline)) {  // candidate for column k1: |x[k1]| or -1
         const double wm = wave_max(v);
         const unsigned long long bl = __ballot(v == wm);
-        if (lane == __ffsll((unsigned long long)bl) - 1) {
+        if (wm < 0.0) {
+            // no candidate row on this wavefront: only the header, which never wins
+            if (lane == 0) hdr[((k1 & 1) * kLW + wave) * 4] = wm;
+        } else if (lane == __ffsll((unsigned long long)bl) - 1) {
             // one lane writes: single stores straight from the row registers
             volatile lds_f64 *h = (volatile lds_f64 *)(hdr + ((k1 & 1) * kLW + wave) * 4);
             h[0] = wm;
@@ -559,7 +552,15 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
             __syncthreads();
         }
     }
-    const double tinyC = group_max(dmax, t, kLT, red) * 0x1p-45;
+    // waves 2 and 3 take the rows of [X v1] (row j on lane 128 + j) into
+    // their row registers, unused by the Cholesky: the LDS area of [X v1] is
+    // then free for L
+    if (!bad && wave >= 2 && t - 128 < M) {
+        const double *xr = Xs + (t - 128) * ldx;
+#pragma unroll
+        for (int j = 0; j < KB; ++j) x[j] = j <= K ? xr[j] : 0.0;
+    }
+    const double tinyC = group_max(dmax, t, kLT, red) * 0x1p-45;  // (its barriers also order the reads above)
     const int ci = t;
     const bool crow = ci <= K;
     if (!bad && ci == K) {
@@ -590,26 +591,32 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
             }
         }
     }
+    double *Lp = xreg;  // strictly lower rows of L, row i at i (i - 1) / 2
     if (!bad) {
-        if (ci == K) {
+        if (ci < K) {
+#pragma unroll
+            for (int j = 0; j < KB; ++j)
+                if (j < ci) Lp[ci * (ci - 1) / 2 + j] = x[j];
+        } else if (ci == K) {
 #pragma unroll
             for (int j = 0; j < KB; ++j)
                 if (j < K) yv[j] = x[j];
         }
         __syncthreads();
-        // L^T z = L^{-1} r: z_k from the column-k products of the rows below
-        double zi = 0.0;
-#pragma unroll
-        for (int k = KB - 1; k >= 0; --k) {
-            if (k < K) {
-                double p = (ci > k && ci < K) ? x[k] * zi : 0.0;
-                p = wave_sum(p);
-                if (lane == 0 && wave < 2) part[(k & 1) * 2 + wave] = p;
-                __syncthreads();
-                if (ci == k) zi = (yv[k] - (part[(k & 1) * 2] + part[(k & 1) * 2 + 1])) * ldiag[k];
+        // L^T z = L^{-1} r by one wavefront, right-looking: z_k from lane
+        // k mod 64, then rows i < k lose L[k][i] z_k (rows i and i + 64 on lane i)
+        if (wave == 0) {
+            double r0 = lane < K ? yv[lane] : 0.0, r1 = lane + 64 < K ? yv[lane + 64] : 0.0;
+            for (int k = K - 1; k >= 0; --k) {
+                const double *lk = Lp + k * (k - 1) / 2;
+                const double l0 = lane < k ? lk[lane] : 0.0;
+                const double l1 = lane + 64 < k ? lk[lane + 64] : 0.0;
+                const double zk = (k < 64 ? lane_value(r0, k) : lane_value(r1, k - 64)) * ldiag[k];
+                if (lane == 0) zv[k] = zk;
+                r0 = fma(-l0, zk, r0);
+                r1 = fma(-l1, zk, r1);
             }
         }
-        if (ci < K) zv[ci] = zi;
         __syncthreads();
     }
 
@@ -621,16 +628,19 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     } else {
         const double s2 = op ? s : s * s;  // degree -2 (Laplacian) or -1 (derivative)
         for (int q = t; q < K; q += kLT) w[inp[q]] = zv[q] / s2;
-        for (int j = t; j < M; j += kLT) {
-            const double *xr = Xs + j * ldx;
-            double a0 = xr[K], a1 = 0.0;
-            int q = 0;
-            for (; q + 1 < K; q += 2) {
-                a0 = fma(xr[q], zv[q], a0);
-                a1 = fma(xr[q + 1], zv[q + 1], a1);
+        // pivot rows: v1_j + (X z)_j from the row registers of waves 2 and 3
+        if (wave >= 2 && t - 128 < M) {
+            double a0 = 0.0, a1 = 0.0, v1 = 0.0;
+#pragma unroll
+            for (int j = 0; j < KB; ++j) {
+                if (j < K) {
+                    if (j & 1) a1 = fma(x[j], zv[j], a1);
+                    else a0 = fma(x[j], zv[j], a0);
+                } else if (j == K) {
+                    v1 = x[j];
+                }
             }
-            if (q < K) a0 = fma(xr[q], zv[q], a0);
-            w[ipiv[j]] = (a0 + a1) / s2;
+            w[ipiv[t - 128]] = (v1 + (a0 + a1)) / s2;
         }
     }
     __syncthreads();
