@@ -860,6 +860,66 @@ def calibrate_copy(nbytes=1 << 30, reps=10):
                       "launches": reps}))
 
 
+def _counter_per_dispatch(csv_dir, match, largest=False):
+    """Mean counter value (KiB) per dispatch of the most often dispatched
+    kernel whose name contains `match` (the timed launches), from a rocprofv3
+    --pmc csv output directory (one counter per run); its name and dispatch
+    count too."""
+    import csv
+    import glob
+    vals = {}
+    for path in glob.glob(os.path.join(csv_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if match in r["Kernel_Name"]:
+                    per = vals.setdefault(r["Kernel_Name"], {})
+                    d = (path, r["Dispatch_Id"])
+                    per[d] = per.get(d, 0.0) + float(r["Counter_Value"])
+    if not vals:
+        raise SystemExit(f"no dispatch of {match!r} under {csv_dir}")
+    name, per = max(vals.items(), key=lambda kv: len(kv[1]))
+    v = list(per.values())
+    if largest:  # only the big launches (the calibration copies, not incidental small ones)
+        v = [x for x in v if x >= 0.5 * max(v)]
+    return sum(v) / len(v), len(v), name
+
+
+def record_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, bench_json):
+    """Write the HBM traffic of the timed FP64 sweep into profiles/traffic.json
+    from four rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE of the bench
+    line, then of `--calibrate-copy`) and the bench line those runs printed
+    (for the sweep shape and the algorithmic bytes)."""
+    with open(bench_json) as fh:
+        line = json.loads(fh.read().strip().splitlines()[-1])
+    rf = line["roofline"]
+    sh = rf["sweep_shape"]
+    shape = ",".join(str(sh[k]) for k in ("waves", "unroll", "xcd_remap", "pipeline", "zigzag", "codes", "temporal"))
+    kern = "k_sweep_f64<"
+    fetch, nd, kname = _counter_per_dispatch(fetch_dir, kern)
+    write, _, _ = _counter_per_dispatch(write_dir, kern)
+    cfetch, _, _ = _counter_per_dispatch(copy_fetch_dir, "copyBuffer", largest=True)
+    cwrite, _, _ = _counter_per_dispatch(copy_write_dir, "copyBuffer", largest=True)
+    nbytes = 1 << 30
+    fs, ws = nbytes / (cfetch * 1024), nbytes / (cwrite * 1024)
+    entry = {"kernel": kname.replace("(anonymous namespace)::", "").replace("void ", "").replace("rbf::", "").split("(")[0],
+             "kernel_source": sweep_source_hash(), "shape": shape,
+             "fetch_kib_per_dispatch": round(fetch, 1), "write_kib_per_dispatch": round(write, 1),
+             "dispatches": nd, "fetch_scale": round(fs, 5), "write_scale": round(ws, 5),
+             "bytes_per_launch": int(fetch * 1024 * fs + write * 1024 * ws),
+             "fetch_bytes": int(fetch * 1024 * fs), "write_bytes": int(write * 1024 * ws),
+             "alg_bytes": rf["alg_bytes_per_launch"], "format_bytes": rf["format_bytes_per_launch"]}
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        d = {}
+    key = "sweep_f64|cube1M|m4"
+    d[key] = entry
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(d, fh, indent=1)
+    print(json.dumps({key: entry}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -872,6 +932,9 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the 2M-node adjoint block")
     ap.add_argument("--tte-target", type=float, default=1e-6)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--record-traffic", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                           "COPY_WRITE_DIR", "BENCH_JSON"),
+                    help="write profiles/traffic.json from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (no GPU)")
     ap.add_argument("--workload", default="cube1M",
                     choices=["cube1M", "cube1M_fp32", "cube8M", "cube4M_bands", "cube2M_adjoint", "support_sweep",
                              "order_scan", "mixed_bc", "square10k"],
@@ -879,6 +942,9 @@ def main():
     ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32_refine"], help="cube8M: iteration mode")
     ap.add_argument("--directions", type=int, default=32, help="cube2M_adjoint: central-difference directions")
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(*args.record_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
