@@ -907,7 +907,11 @@ def record_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, bench_j
              "dispatches": nd, "fetch_scale": round(fs, 5), "write_scale": round(ws, 5),
              "bytes_per_launch": int(fetch * 1024 * fs + write * 1024 * ws),
              "fetch_bytes": int(fetch * 1024 * fs), "write_bytes": int(write * 1024 * ws),
-             "alg_bytes": rf["alg_bytes_per_launch"], "format_bytes": rf["format_bytes_per_launch"]}
+             # algorithmic bytes: 12n + 16 read and 8 written per interior row
+             "alg_read_bytes": rf["alg_bytes_per_launch"] - 8 * line["config"]["interior_nodes"],
+             "alg_write_bytes": 8 * line["config"]["interior_nodes"],
+             "format_bytes": rf["format_bytes_per_launch"]}
+    entry["bytes_per_launch"] = entry["fetch_bytes"] + entry["write_bytes"]
     try:
         with open(TRAFFIC_FILE) as fh:
             d = json.load(fh)
