@@ -562,7 +562,8 @@ def run_cube2m_adjoint(directions=32, cpu_K=20):
             "first_forward_and_adjoint_s": round(first_s, 3),
             "adjoint_ms_per_step": round(1e3 * (t2 - t1) / K, 4), "forward_ms_per_step": round(1e3 * (t1 - t0) / K, 4),
             "transposed_operator": {k: info[k] for k in ("t_slices", "t_slots", "t_coded_slices", "t_code_mismatches",
-                                                         "t_max_len", "t_waves", "t_unroll", "t_codes")},
+                                                         "t_max_len", "t_waves", "t_unroll", "t_codes",
+                                                         "t_lane_order", "t_masked")},
             "J": loss.item(), "fd_eps": eps, "directions": directions, "max_rel_err_vs_fd": max(errs),
             "median_rel_err_vs_fd": float(np.median(errs)), "rel_errs": errs,
             "cpu_reference_gradient": {"steps": cpu_K, "rel_diff_gpu_vs_oracle": cpu_rel, "oracle_s": round(cpu_s, 2),

@@ -347,6 +347,8 @@ typedef struct {
     int32_t t_waves, t_unroll, t_codes;  /* launch shape of the transposed sweep */
     int64_t ns_systems;     /* weight systems solved by the null-space solver (last rbf_compute_weights) */
     int64_t elim_systems;   /* weight systems solved by Gaussian elimination (same call)               */
+    int32_t t_lane_order;   /* transposed slices hold their rows on lanes by decreasing length */
+    int32_t t_masked;       /* the transposed sweep skips each lane's loads past its own length */
 } rbf_operator_info;
 
 /* Fill *info for the current operator (EINVAL without one). */

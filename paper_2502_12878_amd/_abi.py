@@ -56,7 +56,8 @@ class rbf_operator_info(C.Structure):
                 ("code_mismatches", C.c_int32), ("t_slices", C.c_int64), ("t_slots", C.c_int64),
                 ("t_coded_slices", C.c_int64), ("t_code_mismatches", C.c_int64), ("t_max_len", C.c_int32),
                 ("t_waves", C.c_int32), ("t_unroll", C.c_int32), ("t_codes", C.c_int32),
-                ("ns_systems", C.c_int64), ("elim_systems", C.c_int64)]
+                ("ns_systems", C.c_int64), ("elim_systems", C.c_int64),
+                ("t_lane_order", C.c_int32), ("t_masked", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

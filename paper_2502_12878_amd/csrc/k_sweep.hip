@@ -26,24 +26,41 @@
 namespace rbf {
 namespace {
 
+// Row of lane `lane` of `slice` and its entry count: lanes hold rows in
+// order unless the operator has a lane order (Ell::lmeta).
+struct LaneRow {
+    int64_t row;
+    int len;
+};
+template <bool ORDERED>
+__device__ __forceinline__ LaneRow lane_row(const uint16_t *__restrict__ lmeta, int64_t slice, int lane, int len) {
+    if (ORDERED || lmeta) {
+        const int m = lmeta[slice * kSlice + lane];
+        return LaneRow{slice * kSlice + (m & (kSlice - 1)), m >> 6};
+    }
+    return LaneRow{slice * kSlice + lane, len};
+}
+
 // One explicit step on every interior row; optionally max |rho| into slot.
 template <int WAVES, int U, int LAYOUT, bool REDUCE>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep_f64(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
-    const double *__restrict__ w, Codes cs, int64_t s0, int64_t nslices, int64_t N_int, int64_t ncols,
-    const double *__restrict__ f, const double *__restrict__ u_old, double *__restrict__ u_new, double dt,
-    unsigned long long *res_slot, int order) {
+    const double *__restrict__ w, Codes cs, const uint16_t *__restrict__ lmeta, int64_t s0, int64_t nslices,
+    int64_t N_int, int64_t ncols, const double *__restrict__ f, const double *__restrict__ u_old,
+    double *__restrict__ u_new, double dt, unsigned long long *res_slot, int order) {
     const int64_t local = slice_index<WAVES>(nslices, order);
     const int64_t slice = s0 + local;
     const int lane = threadIdx.x & 63;
     unsigned long long bits = 0;
     if (local < nslices) {
         const int len = slice_len[slice];
-        const int64_t row = slice * kSlice + lane;
+        const LaneRow lr = lane_row<LAYOUT == 7>(lmeta, slice, lane, len);
+        const int64_t row = lr.row;
         const bool live = row < N_int;
         const double fr = live ? f[row] : 0.0;  // requested with the slice's descriptors
         const double ur = live ? u_old[row] : 0.0;
-        const double acc = row_dot<double, U, LAYOUT>(cs, slice_ptr, idx, w, BufGather<double>(u_old, ncols), slice, lane, len);
+        const double acc =
+            row_dot<double, U, LAYOUT>(cs, slice_ptr, idx, w, BufGather<double>(u_old, ncols), slice, lane, len, lr.len);
         if (live) {
             const double rho = acc - fr;
             u_new[row] = ur + dt * rho;
@@ -75,15 +92,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_f32(
 template <int WAVES, int U, int LAYOUT>
 __global__ __launch_bounds__(WAVES * 64) void k_apply_f64(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
-    const double *__restrict__ w, int64_t nslices, int64_t N_int, int64_t ncols, const double *__restrict__ u,
-    double *__restrict__ Lu, const double *__restrict__ f, unsigned long long *res_slot, int order) {
+    const double *__restrict__ w, const uint16_t *__restrict__ lmeta, int64_t nslices, int64_t N_int, int64_t ncols,
+    const double *__restrict__ u, double *__restrict__ Lu, const double *__restrict__ f,
+    unsigned long long *res_slot, int order) {
     const int64_t slice = slice_index<WAVES>(nslices, order);
     const int lane = threadIdx.x & 63;
     unsigned long long bits = 0;
     if (slice < nslices) {
         const int len = slice_len[slice];
         const double acc = RowDot<double, U, LAYOUT>::run(idx, w, BufGather<double>(u, ncols), slice_ptr[slice], lane, len);
-        const int64_t row = slice * kSlice + lane;
+        const int64_t row = lane_row<false>(lmeta, slice, lane, len).row;
         if (row < N_int) {
             if (Lu) Lu[row] = acc;
             if (f) bits = (unsigned long long)__double_as_longlong(fabs(acc - f[row]));
@@ -132,11 +150,15 @@ hipError_t dispatch_shape(const SweepCfg &c, int layout, A &&...a) {
     return hipErrorInvalidValue;
 }
 
-// The same over the shapes of the sweeps that read codes (LAYOUT 3 to 6).
-template <template <int, int, int> class F, typename... A>
-hipError_t dispatch_codes(const SweepCfg &c, A &&...a) {
+// The same over the shapes of the sweeps that read codes (LAYOUT 3 to 6, and
+// 7: layout 6 with each lane's loads masked past its row's length, for FP64
+// sweeps of an operator with a lane order).
+template <template <int, int, int> class F, bool MASKABLE, typename... A>
+hipError_t dispatch_codes(const SweepCfg &c, bool masked, A &&...a) {
 #define RBF_CASE(WV, UN) \
     if (c.waves_per_block == WV && c.unroll == UN) {                                                \
+        if constexpr (MASKABLE)                                                                     \
+            if (masked && c.temporal && c.pipeline) return F<WV, UN, 7>::run(a...);                 \
         if (c.temporal) return c.pipeline ? F<WV, UN, 6>::run(a...) : F<WV, UN, 5>::run(a...);      \
         return c.pipeline ? F<WV, UN, 4>::run(a...) : F<WV, UN, 3>::run(a...);                       \
     }
@@ -161,10 +183,12 @@ struct SweepF64 {
         const Codes cs = codes_of(e);
         if (slot)
             hipLaunchKernelGGL((k_sweep_f64<WV, UN, LY, true>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr,
-                               e.slice_len, e.idx, e.w, cs, s0, ns, N_int, e.ncols, f, uo, un, dt, slot, remap);
+                               e.slice_len, e.idx, e.w, cs, e.lmeta, s0, ns, N_int, e.ncols, f, uo, un, dt, slot,
+                               remap);
         else
             hipLaunchKernelGGL((k_sweep_f64<WV, UN, LY, false>), dim3(g), dim3(WV * 64), 0, s, e.slice_ptr,
-                               e.slice_len, e.idx, e.w, cs, s0, ns, N_int, e.ncols, f, uo, un, dt, slot, remap);
+                               e.slice_len, e.idx, e.w, cs, e.lmeta, s0, ns, N_int, e.ncols, f, uo, un, dt, slot,
+                               remap);
         return hipGetLastError();
     }
 };
@@ -187,7 +211,8 @@ struct ApplyF64 {
                           unsigned long long *slot, int remap) {
         if (!e.nslices) return hipSuccess;
         hipLaunchKernelGGL((k_apply_f64<WV, UN, LY>), dim3(grid1d(e.nslices, WV)), dim3(WV * 64), 0, s,
-                           e.slice_ptr, e.slice_len, e.idx, e.w, e.nslices, N_int, e.ncols, u, Lu, f, slot, remap);
+                           e.slice_ptr, e.slice_len, e.idx, e.w, e.lmeta, e.nslices, N_int, e.ncols, u, Lu, f, slot,
+                           remap);
         return hipGetLastError();
     }
 };
@@ -213,8 +238,8 @@ hipError_t launch_sweep_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int6
     if (s0 < 0 || s0 > e.nslices) return hipErrorInvalidValue;
     if (ns < 0 || s0 + ns > e.nslices) ns = e.nslices - s0;
     if (use_codes(c, e))
-        return dispatch_codes<SweepF64>(c, s, e, N_int, f, u_old, u_new, dt, res_slot, order_flags(c, parity), s0,
-                                        ns);
+        return dispatch_codes<SweepF64, true>(c, e.lmeta != nullptr, s, e, N_int, f, u_old, u_new, dt, res_slot,
+                                              order_flags(c, parity), s0, ns);
     return dispatch_shape<SweepF64>(c, e.layout, s, e, N_int, f, u_old, u_new, dt, res_slot, order_flags(c, parity),
                                     s0, ns);
 }
@@ -222,7 +247,7 @@ hipError_t launch_sweep_f64(hipStream_t s, const SweepCfg &c, const Ell &e, int6
 hipError_t launch_sweep_f32(hipStream_t s, const SweepCfg &c, const Ell &e, int64_t N_int, const float *r,
                             const float *e_old, float *e_new, float dt, int parity) {
     if (use_codes(c, e))
-        return dispatch_codes<SweepF32>(c, s, e, N_int, r, e_old, e_new, dt, order_flags(c, parity));
+        return dispatch_codes<SweepF32, false>(c, false, s, e, N_int, r, e_old, e_new, dt, order_flags(c, parity));
     return dispatch_shape<SweepF32>(c, e.layout, s, e, N_int, r, e_old, e_new, dt, order_flags(c, parity));
 }
 

@@ -43,16 +43,19 @@ __device__ __forceinline__ int64_t pair_pos(int64_t base, int k, int lane) {
     return base + (int64_t)(k >> 1) * (2 * kSlice) + 2 * lane + (k & 1);
 }
 
-// Thread per internal column c (and per tail lane of the last slice): sort the
-// column's entries by row, then write them into the sliced layout; padding
-// entries point at c itself with weight 0.
+// Thread per lane of every slice: the lane's column c (lmeta: lanes ordered
+// by decreasing row length; null: c = 64 s + lane) has its entries sorted by
+// row, then written into the sliced layout; padding entries point at c itself
+// with weight 0.
 __global__ void k_tpack(int64_t N_int, int64_t nslices, const int64_t *__restrict__ start,
                         int32_t *__restrict__ rows_t, double *__restrict__ w_t, const int64_t *__restrict__ slice_ptr,
-                        const int32_t *__restrict__ slice_len, int32_t *__restrict__ idx, double *__restrict__ w) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nslices * kSlice) return;
-    const int64_t s = c / kSlice;
-    const int lane = (int)(c - s * kSlice);
+                        const int32_t *__restrict__ slice_len, const uint16_t *__restrict__ lmeta,
+                        int32_t *__restrict__ idx, double *__restrict__ w) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nslices * kSlice) return;
+    const int64_t s = t / kSlice;
+    const int lane = (int)(t - s * kSlice);
+    const int64_t c = lmeta ? s * kSlice + (lmeta[t] & (kSlice - 1)) : t;
     const int len = slice_len[s];
     const int64_t base = slice_ptr[s];
     int cnt = 0;
@@ -108,7 +111,7 @@ hipError_t launch_tpack(hipStream_t s, int64_t N_int, const int64_t *start, int3
                         const Ell &e) {
     if (!e.nslices) return hipSuccess;
     hipLaunchKernelGGL(k_tpack, dim3(grid1d(e.nslices * kSlice, 256)), dim3(256), 0, s, N_int, e.nslices, start,
-                       rows_t, w_t, e.slice_ptr, e.slice_len, e.idx, e.w);
+                       rows_t, w_t, e.slice_ptr, e.slice_len, e.lmeta, e.idx, e.w);
     return hipGetLastError();
 }
 

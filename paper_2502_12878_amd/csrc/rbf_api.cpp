@@ -124,6 +124,7 @@ void drop_operator(rbf_handle *h) {
     free_t(h, h->ellT.cptr);
     free_t(h, h->ellT.segbase);
     free_t(h, h->ellT.cmode);
+    free_t(h, h->ellT.lmeta);
     h->ellT = Ell{};
     h->cfgT = SweepCfg{};
     h->tunedT = false;
@@ -1233,6 +1234,20 @@ static rbf_status build_transpose(rbf_handle *h) {
     }
     sptr[e.nslices] = acc;
     e.elems = acc;
+    // lanes of each slice by decreasing row length (ties by row), so that the
+    // padding of a slice sits in whole cache lines of its last lanes; none if
+    // a row has 1024 entries or more (16-bit lane descriptors)
+    std::vector<uint16_t> lm;
+    if (e.max_len < 1024) {
+        lm.resize((size_t)e.nslices * kSlice);
+        int q[kSlice];
+        for (int64_t s = 0; s < e.nslices; ++s) {
+            for (int r = 0; r < kSlice; ++r) q[r] = r;
+            auto cnt_of = [&](int r) { return s * kSlice + r < Ni ? ch[s * kSlice + r] : 0; };
+            std::stable_sort(q, q + kSlice, [&](int a, int b) { return cnt_of(a) > cnt_of(b); });
+            for (int p = 0; p < kSlice; ++p) lm[s * kSlice + p] = (uint16_t)(q[p] | (cnt_of(q[p]) << 6));
+        }
+    }
     ALLOC(h, start, int64_t, Ni + 1);
     ALLOC(h, cursor, int32_t, Ni);
     ALLOC(h, rows_t, int32_t, std::max<int64_t>(1, nnz));
@@ -1241,7 +1256,10 @@ static rbf_status build_transpose(rbf_handle *h) {
     ALLOC(h, e.slice_len, int32_t, e.nslices);
     ALLOC(h, e.idx, int32_t, std::max<int64_t>(1, e.elems));
     ALLOC(h, e.w, double, std::max<int64_t>(1, e.elems));
+    if (!lm.empty()) ALLOC(h, e.lmeta, uint16_t, e.nslices * kSlice);
     HIPCHK(h, hipMemcpyAsync(start, st.data(), sizeof(int64_t) * (Ni + 1), hipMemcpyHostToDevice, h->stream));
+    if (e.lmeta)
+        HIPCHK(h, hipMemcpyAsync(e.lmeta, lm.data(), sizeof(uint16_t) * lm.size(), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(e.slice_ptr, sptr.data(), sizeof(int64_t) * (e.nslices + 1), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(e.slice_len, slen.data(), sizeof(int32_t) * e.nslices, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemsetAsync(cursor, 0, sizeof(int32_t) * Ni, h->stream));
@@ -1676,6 +1694,8 @@ extern "C" rbf_status rbf_get_operator_info(const rbf_handle *h, rbf_operator_in
         info->t_waves = h->cfgT.waves_per_block;
         info->t_unroll = h->cfgT.unroll;
         info->t_codes = h->cfgT.codes && t.cmode ? 1 : 0;
+        info->t_lane_order = t.lmeta ? 1 : 0;
+        info->t_masked = info->t_codes && t.lmeta && h->cfgT.temporal && h->cfgT.pipeline ? 1 : 0;
     }
     info->ns_systems = h->w_ns_systems;
     info->elim_systems = h->w_elim_systems;

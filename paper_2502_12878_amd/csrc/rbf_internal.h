@@ -72,6 +72,13 @@ struct Ell {
     int32_t *segbase = nullptr;    // [16 nslices]
     int8_t *cmode = nullptr;       // [nslices] 1: slice has codes
     float *w32q = nullptr;         // [celems] FP32 weights of coded slices in the code layout, or null
+    // Lane order of the transposed operator (rows of uneven length): the 64
+    // rows of a slice sit on its lanes by decreasing length, and lane p of
+    // slice s holds row 64 s + (lmeta[64 s + p] & 63), of lmeta[64 s + p] >> 6
+    // (< 1024) entries.  The sweeps then mask each lane's loads past its own
+    // length, so whole cache lines of padding are not fetched.  Null (also
+    // when a row is longer): lane p holds row 64 s + p.
+    uint16_t *lmeta = nullptr;     // [64 nslices] or null
     int64_t celems = 0;
     int64_t coded_slices = 0;      // slices with cmode 1
     int64_t code_mismatches = 0;   // slices whose codes failed the decode check (kept on 32-bit ids)

@@ -393,6 +393,94 @@ struct RowDotCP {
     }
 };
 
+// RowDotCP with ordinary loads for a lane of rl <= len entries (a lane-ordered
+// operator, Ell::lmeta): the code and weight vectors past the lane's own
+// entries are read through raw buffer resources at an offset beyond their
+// range, which returns 0 without a memory access, so the lines that hold only
+// padding of the slice's shorter lanes are never fetched.  Masked entries add
+// fma(0, x, acc) = acc; the lane's entries are summed in the order of
+// RowDotCP, and the last, partial group gathers only up to the slice length.
+template <int U>
+struct RowDotCM {
+    static_assert(U % 4 == 0, "groups of whole code vectors");
+    template <class X>
+    __device__ static __forceinline__ double run(const uint16_t *__restrict__ code, int32_t segreg,
+                                                 const double *__restrict__ w, const X &x, int lane, int len, int rl) {
+        constexpr uint32_t kOff = 0x80000000u;  // past both ranges: reads 0
+        const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc((void *)code, 0, 0x7fffffff, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc((void *)w, 0, 0x7fffffff, 0x00020000);
+        // code vector r (entries 4r .. 4r + 3) at byte 512 r + 8 lane; weight
+        // pair p (entries 2p, 2p + 1) at byte 1024 p + 16 lane
+        const uint32_t cl = 8u * lane, wl = 16u * lane;
+        auto cload = [&](int r) {
+            const uint32_t off = 4 * r < rl ? 512u * r + cl : kOff;
+            return __builtin_bit_cast(u16x4, __builtin_amdgcn_raw_buffer_load_b64(rc, off, 0, 0));
+        };
+        auto wload = [&](int p) {
+            const uint32_t off = 2 * p < rl ? 1024u * p + wl : kOff;
+            return __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rw, off, 0, 0));
+        };
+        double acc = 0.0;
+        const int full = len / U, groups = (len + U - 1) / U;
+        u16x4 cn[U / 4];
+        f64x2 wn[U / 2];
+        if (groups > 0) {
+#pragma unroll
+            for (int q = 0; q < U / 4; ++q) cn[q] = cload(q);
+#pragma unroll
+            for (int q = 0; q < U / 2; ++q) wn[q] = wload(q);
+        }
+        for (int g = 0; g < full; ++g) {
+            u16x4 cc[U / 4];
+            f64x2 wc[U / 2];
+#pragma unroll
+            for (int q = 0; q < U / 4; ++q) cc[q] = cn[q];
+#pragma unroll
+            for (int q = 0; q < U / 2; ++q) wc[q] = wn[q];
+            if (g + 1 < groups) {
+#pragma unroll
+                for (int q = 0; q < U / 4; ++q) cn[q] = cload((g + 1) * (U / 4) + q);
+#pragma unroll
+                for (int q = 0; q < U / 2; ++q) wn[q] = wload((g + 1) * (U / 2) + q);
+            }
+            double xx[U];
+#pragma unroll
+            for (int q = 0; q < U / 4; ++q) {
+                xx[4 * q] = x[code_col(cc[q].x, segreg)];
+                xx[4 * q + 1] = x[code_col(cc[q].y, segreg)];
+                xx[4 * q + 2] = x[code_col(cc[q].z, segreg)];
+                xx[4 * q + 3] = x[code_col(cc[q].w, segreg)];
+            }
+#pragma unroll
+            for (int q = 0; q < U / 2; ++q) {
+                acc = fma(wc[q].x, xx[2 * q], acc);
+                acc = fma(wc[q].y, xx[2 * q + 1], acc);
+            }
+        }
+        if (full < groups) {  // entries kt .. len - 1, already requested (len is even)
+            const int kt = full * U;
+            double xx[U];
+#pragma unroll
+            for (int q = 0; q < U / 4; ++q)
+                if (kt + 4 * q < len) {
+                    xx[4 * q] = x[code_col(cn[q].x, segreg)];
+                    xx[4 * q + 1] = x[code_col(cn[q].y, segreg)];
+                    if (kt + 4 * q + 2 < len) {
+                        xx[4 * q + 2] = x[code_col(cn[q].z, segreg)];
+                        xx[4 * q + 3] = x[code_col(cn[q].w, segreg)];
+                    }
+                }
+#pragma unroll
+            for (int q = 0; q < U / 2; ++q)
+                if (kt + 2 * q < len) {
+                    acc = fma(wn[q].x, xx[2 * q], acc);
+                    acc = fma(wn[q].y, xx[2 * q + 1], acc);
+                }
+        }
+        return acc;
+    }
+};
+
 // Compressed view of a packed operator handed to the sweep kernels (all null
 // when the plain column ids are read).
 struct Codes {
@@ -405,16 +493,17 @@ struct Codes {
 // Row sum of the calling lane's row of `slice`, from codes where the slice
 // has them, else from the 32-bit ids.
 // LAYOUT 3 / 4 are layouts 1 / 2 read through the codes, 5 / 6 the same with
-// ordinary instead of non-temporal stream loads (kernels compiled for them
-// hold both loops; the others hold only their own, which keeps their
+// ordinary instead of non-temporal stream loads, 7 is 6 with the loads past
+// the lane's rl entries masked (RowDotCM, FP64 only) (kernels compiled for
+// them hold both loops; the others hold only their own, which keeps their
 // registers).
 template <typename T, int U, int LAYOUT, class X>
 __device__ __forceinline__ T row_dot(const Codes &cs, const int64_t *__restrict__ slice_ptr,
                                      const int32_t *__restrict__ idx, const T *__restrict__ w, const X &x,
-                                     int64_t slice, int lane, int len) {
+                                     int64_t slice, int lane, int len, int rl = 0) {
     if constexpr (LAYOUT >= 3) {
-        constexpr bool NT = LAYOUT <= 4;                    // 5 / 6: ordinary stream loads
-        constexpr bool PIPE = LAYOUT == 4 || LAYOUT == 6;
+        constexpr bool NT = LAYOUT <= 4;                    // 5 / 6 / 7: ordinary stream loads
+        constexpr bool PIPE = LAYOUT == 4 || LAYOUT >= 6;
         // the slice's descriptors in one round trip (segbase and cptr exist,
         // unused, for slices without codes)
         const int8_t coded = cs.cmode[slice];
@@ -422,7 +511,9 @@ __device__ __forceinline__ T row_dot(const Codes &cs, const int64_t *__restrict_
         const int64_t cbase = cs.cptr[slice];
         const int64_t sbase = slice_ptr[slice];
         if (coded) {
-            if constexpr (PIPE)
+            if constexpr (LAYOUT == 7)
+                return RowDotCM<U>::run(cs.code + cbase, segreg, w + sbase, x, lane, len, rl);
+            else if constexpr (PIPE)
                 return RowDotCP<T, U, NT>::run(cs.code + cbase, segreg, w + sbase, x, lane, len);
             else
                 return RowDotC<T, U, NT>::run(cs.code + cbase, segreg, w + sbase, x, lane, len);

@@ -83,6 +83,9 @@ def test_transpose_and_adjoint_large_supports(side, m, n, seed, monkeypatch):
         grads.append(q.adjoint_f(dev(gK), K, every, dt).cpu().numpy())
         qi = q.operator_info()
         assert qi["t_codes"] == int(shape.split(",")[5]) and qi["t_code_mismatches"] == 0
+        assert qi["t_lane_order"] == 1
+        # codes, ordinary loads, pipelined: the masked sweep
+        assert qi["t_masked"] == (1 if shape.startswith("4,16,0,1,1,1,1") else 0)
         q.close()
     monkeypatch.delenv("RBF_SWEEP_SHAPE")
     for g in grads[1:]:
