@@ -211,22 +211,38 @@ bool cache_lookup(const std::string &key, int *vals, int nv) {
     return true;
 }
 
+// Rewrites the file with one entry per line: every "key": [ints] entry found
+// in it (values may span lines), except the old entry of `key`, then `key`.
 void cache_store(const std::string &key, const int *vals, int nv) {
     const std::string path = cache_path();
     if (path.empty()) return;
-    std::string s = read_file(path);
+    const std::string s = read_file(path);
     std::vector<std::string> lines;
-    {
-        std::stringstream ss(s);
-        std::string line;
-        while (std::getline(ss, line)) {
-            const size_t q = line.find('"');
-            if (q == std::string::npos) continue;
-            if (line.find("\"" + key + "\"") != std::string::npos) continue;
-            std::string l = line;
-            while (!l.empty() && (l.back() == ',' || l.back() == ' ')) l.pop_back();
-            lines.push_back(l);
+    for (size_t at = 0;;) {
+        const size_t k0 = s.find('"', at);
+        if (k0 == std::string::npos) break;
+        const size_t k1 = s.find('"', k0 + 1);
+        if (k1 == std::string::npos) break;
+        const size_t b0 = s.find_first_not_of(" \t\r\n", k1 + 1);
+        if (b0 == std::string::npos || s[b0] != ':') { at = k1 + 1; continue; }
+        const size_t v0 = s.find_first_not_of(" \t\r\n", b0 + 1);
+        if (v0 == std::string::npos || s[v0] != '[') { at = k1 + 1; continue; }
+        const size_t v1 = s.find(']', v0);
+        if (v1 == std::string::npos) break;
+        at = v1 + 1;
+        const std::string k = s.substr(k0 + 1, k1 - k0 - 1);
+        if (k == key) continue;
+        std::string l = "  \"" + k + "\": [";
+        std::stringstream vs(s.substr(v0 + 1, v1 - v0 - 1));
+        std::string tok;
+        bool first = true, ok = true;
+        while (std::getline(vs, tok, ',')) {
+            const size_t t0 = tok.find_first_not_of(" \t\r\n"), t1 = tok.find_last_not_of(" \t\r\n");
+            if (t0 == std::string::npos) { ok = false; break; }
+            l += (first ? "" : ", ") + tok.substr(t0, t1 - t0 + 1);
+            first = false;
         }
+        if (ok && !first) lines.push_back(l + "]");
     }
     std::string entry = "  \"" + key + "\": [";
     for (int i = 0; i < nv; ++i) entry += (i ? ", " : "") + std::to_string(vals[i]);

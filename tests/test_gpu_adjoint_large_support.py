@@ -5,7 +5,8 @@ so a row's length is a column's in-degree: how many interior supports hold
 that node.  The support size does not bound it (3D, n = 256: up to ~320), so
 the transposed rows are longer than any forward row.  These tests run the
 transposed product and the adjoint gradient (Sec. II-C step, Horner form) at
-n = 168 and n = 256 against the oracle's scatter loops on the same operator,
+n = 168 and n = 256, and at n = 70 on a node set whose ids span two 4096-id
+code segments, against the oracle's scatter loops on the same operator,
 to 1e-11 relative, with the transposed codes checked on the device and the
 result independent of the sweep shape.
 """
@@ -30,7 +31,9 @@ def _rel(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
 
-@pytest.mark.parametrize("side,m,n,seed", [(14, 4, 168, 41), (16, 4, 256, 41)])
+# side 22: 8,000 interior ids in two 4096-id blocks, so transposed slices read
+# codes of more than one segment (their bases come from other lanes)
+@pytest.mark.parametrize("side,m,n,seed", [(14, 4, 168, 41), (16, 4, 256, 41), (22, 4, 70, 43)])
 def test_transpose_and_adjoint_large_supports(side, m, n, seed, monkeypatch):
     import torch
 
@@ -68,7 +71,7 @@ def test_transpose_and_adjoint_large_supports(side, m, n, seed, monkeypatch):
     info = p.operator_info()
     assert info["t_max_len"] == int(deg.max()) + (int(deg.max()) & 1)
     assert info["t_code_mismatches"] == 0 and info["code_mismatches"] == 0
-    # every id of this node set lies in one 4096-id block: every slice has codes
+    # the interior ids span at most two 4096-id blocks: every slice has codes
     assert info["t_coded_slices"] == info["t_slices"] > 0
     K, every = 60, 20
     gK = rng.standard_normal(len(typ))
