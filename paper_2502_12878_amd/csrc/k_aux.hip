@@ -161,7 +161,10 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_ell(
 // With u_cur / u_next (supports of interior nodes and the row itself only, so
 // no Neumann row reads another's value) the new value goes straight into both
 // iterate buffers.  With g null, nb[N_int + j] = (D u)_j instead (the
-// derivative).
+// derivative).  The update is bound by its chain of dependent loads, so the
+// chain is kept short: with ulen > 0 (every slice that long) the slice's
+// place is computed instead of read, and the row's own values (g, its own
+// weight) are requested before the stream loads.
 constexpr int kNeuWaves = 8;
 constexpr int kNeuBatch = 8;  // entry pairs per batch
 
@@ -169,12 +172,19 @@ template <int LAYOUT>
 __global__ __launch_bounds__(kNeuWaves * 64) void k_neumann_eval(
     const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ slice_len, const int32_t *__restrict__ idx,
     const double *__restrict__ w, int64_t N_int, int64_t N_neu, const double *__restrict__ wself,
-    const double *__restrict__ g, const double *u, double *__restrict__ nb, double *u_cur, double *u_next) {
+    const double *__restrict__ g, const double *u, double *__restrict__ nb, double *u_cur, double *u_next,
+    int ulen) {
     __shared__ double part[kNeuWaves][kSlice];
     const int64_t slice = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int len = slice_len[slice];
-    const int64_t base = slice_ptr[slice];
+    const int64_t jr = slice * kSlice + lane;
+    double own = 0.0, ws = 1.0;  // g (or u) and the own weight of row jr, requested first
+    if (wave == 0 && jr < N_neu) {
+        ws = wself[jr];
+        own = g ? g[N_int + jr] : u[N_int + jr];
+    }
+    const int len = ulen > 0 ? ulen : slice_len[slice];
+    const int64_t base = ulen > 0 ? slice * (int64_t)ulen * kSlice : slice_ptr[slice];
     double acc = 0.0;
     if (LAYOUT == 1) {
         // entry pairs as vectors (len is even): wavefront q takes pairs [p0, p1)
@@ -219,10 +229,9 @@ __global__ __launch_bounds__(kNeuWaves * 64) void k_neumann_eval(
     acc = 0.0;
 #pragma unroll
     for (int q = 0; q < kNeuWaves; ++q) acc += part[q][lane];
-    const int64_t jr = slice * kSlice + lane;
     if (jr >= N_neu) return;
     if (g) {
-        const double v = (g[N_int + jr] - acc) / wself[jr];
+        const double v = (own - acc) / ws;
         if (u_cur) {
             u_cur[N_int + jr] = v;
             u_next[N_int + jr] = v;
@@ -230,7 +239,7 @@ __global__ __launch_bounds__(kNeuWaves * 64) void k_neumann_eval(
             nb[jr] = v;
         }
     } else {
-        nb[N_int + jr] = acc + wself[jr] * u[N_int + jr];
+        nb[N_int + jr] = acc + ws * own;
     }
 }
 
@@ -425,10 +434,10 @@ hipError_t launch_neumann_update(hipStream_t s, const Ell &e, int64_t N_int, int
     double *uc = direct ? u_cur : nullptr, *un = direct ? u_next : nullptr;
     if (e.layout)
         hipLaunchKernelGGL(k_neumann_eval<1>, grid, dim3(kNeuWaves * 64), 0, s, e.slice_ptr, e.slice_len, e.idx, e.w, N_int,
-                           N_neu, wself, g, u_cur, nb, uc, un);
+                           N_neu, wself, g, u_cur, nb, uc, un, e.uniform_len);
     else
         hipLaunchKernelGGL(k_neumann_eval<0>, grid, dim3(kNeuWaves * 64), 0, s, e.slice_ptr, e.slice_len, e.idx, e.w, N_int,
-                           N_neu, wself, g, u_cur, nb, uc, un);
+                           N_neu, wself, g, u_cur, nb, uc, un, e.uniform_len);
     if (!direct)
         hipLaunchKernelGGL(k_neumann_store, dim3(grid1d(N_neu, 256)), dim3(256), 0, s, N_int, N_neu, nb, u_cur,
                            u_next);
@@ -442,10 +451,10 @@ hipError_t launch_neumann_apply(hipStream_t s, const Ell &e, int64_t N_int, int6
     const dim3 grid((unsigned)e.nslices);
     if (e.layout)
         hipLaunchKernelGGL(k_neumann_eval<1>, grid, dim3(kNeuWaves * 64), 0, s, e.slice_ptr, e.slice_len, e.idx, e.w, N_int,
-                           N_neu, wself, nullptr, u, out, nullptr, nullptr);
+                           N_neu, wself, nullptr, u, out, nullptr, nullptr, e.uniform_len);
     else
         hipLaunchKernelGGL(k_neumann_eval<0>, grid, dim3(kNeuWaves * 64), 0, s, e.slice_ptr, e.slice_len, e.idx, e.w, N_int,
-                           N_neu, wself, nullptr, u, out, nullptr, nullptr);
+                           N_neu, wself, nullptr, u, out, nullptr, nullptr, e.uniform_len);
     return hipGetLastError();
 }
 

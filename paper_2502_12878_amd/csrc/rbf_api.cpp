@@ -681,6 +681,9 @@ static rbf_status make_ell(rbf_handle *h, int64_t row0, int64_t nrows, const std
     sptr[e.nslices] = acc;
     e.elems = acc;
     e.max_len = mx;
+    e.uniform_len = mx;
+    for (int64_t s = 0; s < e.nslices; ++s)
+        if (slen[s] != mx) e.uniform_len = 0;
     ALLOC(h, e.slice_ptr, int64_t, e.nslices + 1);
     ALLOC(h, e.slice_len, int32_t, std::max<int64_t>(1, e.nslices));
     ALLOC(h, e.idx, int32_t, std::max<int64_t>(1, e.elems));

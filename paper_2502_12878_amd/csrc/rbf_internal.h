@@ -56,6 +56,7 @@ struct Ell {
     int64_t elems = 0;
     int64_t ncols = 0;             // length of the gathered vector (all nodes)
     int32_t max_len = 0;
+    int32_t uniform_len = 0;       // the length of every slice when all are equal, else 0
     int64_t *slice_ptr = nullptr;  // [nslices + 1]
     int32_t *slice_len = nullptr;  // [nslices]
     int32_t *idx = nullptr;        // [elems] internal ids
