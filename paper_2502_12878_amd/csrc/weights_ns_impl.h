@@ -35,9 +35,12 @@
 //      blocks, or C_aug[block, .] += T for the others.  C_aug = [G v]^T A
 //      [G v] (lower tiles, in registers) holds C and, in its last row,
 //      (G^T A v)^T;
-//   5. Cholesky of C, one row per lane, with the reduced right-hand side as
-//      an extra row (its multipliers are L^{-1} r); backward substitution by
-//      per-step reductions; w = v + G z back in support order.
+//   5. Cholesky of C on those tiles, with the reduced right-hand side as an
+//      extra row (its multipliers are L^{-1} r): per column block its owning
+//      wavefront factors the block in registers (DPP and lane permutes, no
+//      barrier), then every wavefront updates its later blocks by L_ap L_bp^T
+//      on the matrix cores; backward substitution by blocks from the same
+//      tiles; w = v + G z back in support order.
 // Singular systems: an LU pivot at most 2^-45 max|P| (the supports cannot fix
 // the monomials: too few or degenerate nodes) or a Cholesky pivot at most
 // 2^-45 max C_ii (e.g. duplicate nodes) report ESINGULAR.
@@ -74,7 +77,7 @@ __host__ __device__ inline LuLayout lu_layout(int n, int M, int MB, int KB) {
     L.nJ = (L.K + 1 + 15) / 16;
     L.ldx = L.K + 1;          // [X v1], row-major (M rows)
     L.lda = L.M4 + 1;         // block of A: odd stride, the 16 rows of a fragment in distinct banks
-    L.ldst = 16 * L.nJ;       // staging rows of C_aug
+    L.ldst = 16 * L.nJ;       // 16 ldst: one column block's L tiles
     int o = 0;
     L.y = o;
     o += 3 * n + (n & 1);
@@ -94,7 +97,7 @@ __host__ __device__ inline LuLayout lu_layout(int n, int M, int MB, int KB) {
     if (l1_off(M) + 2 > xr) xr = l1_off(M) + 2;
     if (M * L.ldx > xr) xr = M * L.ldx;
     o += xr + (xr & 1);
-    L.treg = o;                // block of A, then C_aug staging, then Cholesky columns
+    L.treg = o;                // block of A, then a column block's L tiles
     int tr = 16 * L.lda;
     if (16 * L.ldst > tr) tr = 16 * L.ldst;
     if (2 * (KB + 2) > tr) tr = 2 * (KB + 2);
@@ -120,6 +123,42 @@ __device__ __forceinline__ double lane_value(double v, int l) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
     return __hiloint2double(hi, lo);
+}
+
+// Value of lane src (any lane of the wavefront) by the LDS crossbar (no LDS
+// memory).  Every lane must be active.
+__device__ __forceinline__ double lane_perm(double v, int src) {
+    const int a = src << 2;
+    const int lo = __builtin_amdgcn_ds_bpermute(a, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(a, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Value of lane N of the calling lane's row of 16 (DPP row_newbcast, one
+// 64-bit move).  Every lane of the row must be active.
+template <int N>
+__device__ __forceinline__ double row_bcast(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + N, 0xF, 0xF, false);
+}
+__device__ __forceinline__ double row_bcast(double v, int n) {  // n a constant once unrolled
+    switch (n) {
+    case 0: return row_bcast<0>(v);
+    case 1: return row_bcast<1>(v);
+    case 2: return row_bcast<2>(v);
+    case 3: return row_bcast<3>(v);
+    case 4: return row_bcast<4>(v);
+    case 5: return row_bcast<5>(v);
+    case 6: return row_bcast<6>(v);
+    case 7: return row_bcast<7>(v);
+    case 8: return row_bcast<8>(v);
+    case 9: return row_bcast<9>(v);
+    case 10: return row_bcast<10>(v);
+    case 11: return row_bcast<11>(v);
+    case 12: return row_bcast<12>(v);
+    case 13: return row_bcast<13>(v);
+    case 14: return row_bcast<14>(v);
+    default: return row_bcast<15>(v);
+    }
 }
 
 // Maximum over the wavefront, the same value on every lane: within each row
@@ -304,8 +343,9 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     bad = !(s > 0.0);
     bool isfree = row < n;
     int mystep = -1;
-    // candidates, double-buffered: per wavefront a header (|pivot|, row,
-    // pivot) and the row's entries past the pivot column
+    // candidates, double-buffered: per wavefront a header (|pivot|, row, -,
+    // 1 / pivot) and the row's entries past the pivot column; the
+    // posting lane divides while its row stores drain, off the step's path
     double *hdr = xreg;                    // [2][kLW][4]
     double *slots = xreg + 8 * kLW;        // [2][kLW][MB]
     auto post = [&](int k1, double v) __attribute__((always_inline)) {  // candidate for column k1: |x[k1]| or -1
@@ -321,10 +361,11 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
             h[1] = (double)row;
             volatile lds_f64 *sl = (volatile lds_f64 *)(slots + opaque(((k1 & 1) * kLW + wave) * MB));
 #pragma unroll
-            for (int j = 0; j < MB; ++j) {
-                if (j == k1) h[2] = x[j];
+            for (int j = 0; j < MB; ++j)
                 if (j > k1) sl[j] = x[j];
-            }
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+                if (j == k1) h[3] = 1.0 / x[j];
         }
     };
     post(0, isfree ? fabs(x[0]) : -1.0);
@@ -333,7 +374,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     for (int k = 0; k < MB; ++k) {
         if (k < M && !bad) {
             const double *hb = hdr + (k & 1) * kLW * 4;
-            double best = hb[0], pv = hb[2];
+            double best = hb[0], rpv = hb[3];
             int bw = 0, prow = (int)hb[1];
 #pragma unroll
             for (int w = 1; w < kLW; ++w) {
@@ -341,7 +382,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
                 if (v > best) {
                     best = v;
                     bw = w;
-                    pv = hb[4 * w + 2];
+                    rpv = hb[4 * w + 3];
                     prow = (int)hb[4 * w + 1];
                 }
             }
@@ -349,7 +390,6 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
                 bad = true;  // uniform: every thread read the same candidates
             } else {
                 const double *u = slots + opaque(((k & 1) * kLW + bw) * MB);
-                const double rpv = 1.0 / pv;
                 if (row == prow) {
                     isfree = false;
                     mystep = k;
@@ -507,8 +547,18 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
         }
     }
 
-    // ---- 5. Cholesky of C with the reduced right-hand side as row K
-    // r = G^T b1 - G^T A v: X^T b1[pivots] + b1[non-pivots] - C_aug[K, 0..K-1]
+    // ---- 5. Cholesky of C_aug's leading K x K block with the reduced
+    // right-hand side r = G^T b1 - G^T A v as row K (its multipliers are
+    // L^{-1} r), on the tiles the matrix cores left in registers: tile (a, b)
+    // belongs to the wavefront of column block b, lane l element e holding
+    // row 16 a + l / 16 + 4 e, column 16 b + l % 16.  Per column block p the
+    // owner factors the block's 16 columns inside the wavefront (column k
+    // reaches each row of 16 lanes by DPP, row k of the diagonal tile by a
+    // lane permute: no barrier), stages the block's L tiles in LDS, and after
+    // one barrier every wavefront subtracts L_ap L_bp^T from its tiles (a, b),
+    // b > p, on the matrix cores.  Then L^T z = L^{-1} r by blocks, from p =
+    // nJ - 1 down, each owner with its own tiles.
+    int *cflag = (int *)(misc + 16);  // a pivot failed in some owner's block
     if (!bad && t < K) {
         double a0 = 0.0, a1 = 0.0;
         int j = 0;
@@ -519,105 +569,139 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
         if (j < M) a0 = fma(Xs[j * ldx + t], b1[ipiv[j]], a0);
         rhs[t] = (a0 + a1) + b1[inp[t]];
     }
-    // lower tiles of C_aug to one row per lane (rows 0..K), by row blocks
-    double x[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) x[j] = 0.0;
+    if (t == 0) *cflag = 0;
+    __syncthreads();
+    double *stg = treg;  // L tiles (a, p), a > p, of the current block: column-major 16 x 16 at 256 (a - p)
+    // row K := r_j - C_aug[K][j] for j < K, 0 past it; the largest diagonal
     double dmax = 0.0;
+    auto prep = [&](auto &T, int cb) __attribute__((always_inline)) {
+        constexpr int NT = sizeof(T) / sizeof(T[0]);
+        if (cb < 0) return;
+#pragma unroll
+        for (int d = 0; d < NT; ++d)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = 16 * (cb + d) + lq + 4 * r, gj = 16 * cb + l16;
+                if (gi == K) T[d][r] = gj < K ? rhs[gj] - T[d][r] : 0.0;
+                if (d == 0 && gi == gj && gi < K) dmax = fmax(dmax, T[d][r]);
+            }
+    };
     if (!bad) {
-        double *st = treg;
-        const int ldst = L.ldst;
-        for (int a = 0; a < nJ; ++a) {
-#pragma unroll
-            for (int d = 0; d < 6; ++d) {
-                if (cb0 >= 0 && cb0 + d == a) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) st[(lq + 4 * r) * ldst + 16 * cb0 + l16] = acc0[d][r];
-                }
-            }
-#pragma unroll
-            for (int d = 0; d < 2; ++d) {
-                if (cb1 >= 0 && cb1 + d == a) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) st[(lq + 4 * r) * ldst + 16 * cb1 + l16] = acc1[d][r];
-                }
-            }
-            __syncthreads();
-            if (t >= 16 * a && t < 16 * a + 16 && t <= K) {
-                const double *sr = st + (t - 16 * a) * ldst;
-#pragma unroll
-                for (int j = 0; j < KB; ++j) x[j] = j <= t ? sr[j] : 0.0;
-                if (t < K) dmax = sr[t];
-            }
-            __syncthreads();
-        }
+        prep(acc0, cb0);
+        prep(acc1, cb1);
     }
-    // waves 2 and 3 take the rows of [X v1] (row j on lane 128 + j) into
-    // their row registers, unused by the Cholesky: the LDS area of [X v1] is
-    // then free for L
-    if (!bad && wave >= 2 && t - 128 < M) {
-        const double *xr = Xs + (t - 128) * ldx;
+    const double tinyC = group_max(dmax, t, kLT, red) * 0x1p-45;
+    // in-wavefront factorization of column block cb (diagonal tile T[0]);
+    // L's row K multipliers go to yv, 1 / L[k][k] to ldiag
+    auto factor = [&](auto &T, int cb) __attribute__((always_inline)) {
+        constexpr int NT = sizeof(T) / sizeof(T[0]);
 #pragma unroll
-        for (int j = 0; j < KB; ++j) x[j] = j <= K ? xr[j] : 0.0;
-    }
-    const double tinyC = group_max(dmax, t, kLT, red) * 0x1p-45;  // (its barriers also order the reads above)
-    const int ci = t;
-    const bool crow = ci <= K;
-    if (!bad && ci == K) {
+        for (int k = 0; k < 16; ++k) {
+            const int gk = 16 * cb + k;
+            if (gk < K && !bad) {
+                const double d = lane_value(T[0][k / 4], (k % 4) * 16 + k);
+                if (!(d > tinyC)) {
+                    bad = true;  // uniform in the wavefront
+                } else {
+                    const double rd = 1.0 / d, rl = sqrt(rd);
+                    const double cjr = lane_perm(T[0][k / 4], (k % 4) * 16 + l16) * rd;  // C[k][j] / d
 #pragma unroll
-        for (int j = 0; j < KB; ++j) x[j] = j < K ? rhs[j] - x[j] : 0.0;
-    }
-    double *colb = treg;  // column k of the updated matrix, double-buffered [2][KB + 2]
+                    for (int dd = 0; dd < NT; ++dd)
+                        if (cb + dd < nJ) {
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-        if (k < K && !bad) {
-            double *cbk = colb + opaque((k & 1) * (KB + 2));
-            if (crow && ci >= k) cbk[ci] = x[k];
-            __syncthreads();
-            const double d = cbk[k];
-            if (!(d > tinyC)) {
-                bad = true;  // uniform
-            } else {
-                const double rd = 1.0 / d;
-                const double rl = sqrt(rd);  // 1 / L[k][k]
-                if (t == 0) ldiag[k] = rl;
-                if (crow && ci > k) {
-                    const double f = x[k] * rd;
-                    // columns up to KB - 1: those past K hold no row entries
-                    // (never read by rows 0..K), so the update stays static
-                    row_axpy<KB, 2>(x, cbk, f, k + 1, KB);
-                    x[k] = x[k] * rl;  // L[ci][k] (row K: (L^{-1} r)_k)
+                            for (int r = 0; r < 4; ++r) {
+                                const int i = lq + 4 * r;
+                                const double ci = row_bcast(T[dd][r], k);  // C[i][k]
+                                const double v = fma(-ci, cjr, T[dd][r]);
+                                T[dd][r] = (l16 > k && (dd > 0 || i > k)) ? v : T[dd][r];
+                                T[dd][r] = (l16 == k && (dd > 0 || i >= k)) ? T[dd][r] * rl : T[dd][r];
+                            }
+                        }
+                    if (lane == 0) ldiag[gk] = rl;
                 }
             }
         }
-    }
-    double *Lp = xreg;  // strictly lower rows of L, row i at i (i - 1) / 2
-    if (!bad) {
-        if (ci < K) {
+        if (bad) {
+            if (lane == 0) *cflag = 1;
+            return;
+        }
 #pragma unroll
-            for (int j = 0; j < KB; ++j)
-                if (j < ci) Lp[ci * (ci - 1) / 2 + j] = x[j];
-        } else if (ci == K) {
+        for (int dd = 0; dd < NT; ++dd)
+            if (cb + dd < nJ) {
 #pragma unroll
-            for (int j = 0; j < KB; ++j)
-                if (j < K) yv[j] = x[j];
+                for (int r = 0; r < 4; ++r) {
+                    const int gi = 16 * (cb + dd) + lq + 4 * r, gj = 16 * cb + l16;
+                    if (gi == K && gj < K) yv[gj] = T[dd][r];
+                    if (dd > 0) stg[(dd * 16 + l16) * 16 + lq + 4 * r] = T[dd][r];
+                }
+            }
+    };
+    // tiles (a, cb), a >= cb > p: T -= L_ap L_cb,p^T (A and B fragments read
+    // alike: lane l takes L[l % 16][4 s + l / 16] of its tile)
+    auto trail = [&](auto &T, int cb, int p) __attribute__((always_inline)) {
+        constexpr int NT = sizeof(T) / sizeof(T[0]);
+        if (cb <= p) return;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const double bv = stg[((cb - p) * 16 + 4 * s4 + lq) * 16 + l16];
+#pragma unroll
+            for (int dd = 0; dd < NT; ++dd)
+                if (cb + dd < nJ) {
+                    const double av = -stg[((cb + dd - p) * 16 + 4 * s4 + lq) * 16 + l16];
+                    T[dd] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, T[dd], 0, 0, 0);
+                }
+        }
+    };
+    for (int p = 0; p < nJ && 16 * p < K; ++p) {
+        if (!bad) {
+            if (cb0 == p) factor(acc0, cb0);
+            else if (cb1 == p) factor(acc1, cb1);
         }
         __syncthreads();
-        // L^T z = L^{-1} r by one wavefront, right-looking: z_k from lane
-        // k mod 64, then rows i < k lose L[k][i] z_k (rows i and i + 64 on lane i)
-        if (wave == 0) {
-            double r0 = lane < K ? yv[lane] : 0.0, r1 = lane + 64 < K ? yv[lane + 64] : 0.0;
-            for (int k = K - 1; k >= 0; --k) {
-                const double *lk = Lp + k * (k - 1) / 2;
-                const double l0 = lane < k ? lk[lane] : 0.0;
-                const double l1 = lane + 64 < k ? lk[lane + 64] : 0.0;
-                const double zk = (k < 64 ? lane_value(r0, k) : lane_value(r1, k - 64)) * ldiag[k];
-                if (lane == 0) zv[k] = zk;
-                r0 = fma(-l0, zk, r0);
-                r1 = fma(-l1, zk, r1);
+        bad = bad || *cflag != 0;
+        if (!bad) {
+            trail(acc0, cb0, p);
+            trail(acc1, cb1, p);
+        }
+        __syncthreads();  // staging rewritten by the next block's owner
+    }
+    // L^T z = L^{-1} r: block p's owner takes s = y_p - sum_{a > p} L_ap^T z_a
+    // from its tiles, then solves with its diagonal tile from k = 15 down
+    auto bsub = [&](auto &T, int cb) __attribute__((always_inline)) {
+        constexpr int NT = sizeof(T) / sizeof(T[0]);
+        double part = 0.0;
+#pragma unroll
+        for (int dd = 1; dd < NT; ++dd)
+            if (cb + dd < nJ) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gi = 16 * (cb + dd) + lq + 4 * r;
+                    part = fma(T[dd][r], gi < K ? zv[gi] : 0.0, part);
+                }
+            }
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        const int gj = 16 * cb + l16;
+        double sj = (gj < K ? yv[gj] : 0.0) - part;
+#pragma unroll
+        for (int k = 15; k >= 0; --k) {
+            const int gk = 16 * cb + k;
+            if (gk < K) {
+                const double zk = lane_value(sj, k) * ldiag[gk];
+                const double lkj = lane_perm(T[0][k / 4], (k % 4) * 16 + l16);  // L[k][j], j < k
+                sj = l16 < k ? fma(-lkj, zk, sj) : sj;
+                if (lane == 0) zv[gk] = zk;
             }
         }
-        __syncthreads();
+    };
+    if (!bad) {
+        for (int p = nJ - 1; p >= 0; --p) {
+            if (16 * p < K) {
+                if (cb0 == p) bsub(acc0, cb0);
+                else if (cb1 == p) bsub(acc1, cb1);
+                __syncthreads();
+            }
+        }
     }
 
     // ---- 6. w = v + G z in support order
@@ -628,19 +712,17 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     } else {
         const double s2 = op ? s : s * s;  // degree -2 (Laplacian) or -1 (derivative)
         for (int q = t; q < K; q += kLT) w[inp[q]] = zv[q] / s2;
-        // pivot rows: v1_j + (X z)_j from the row registers of waves 2 and 3
-        if (wave >= 2 && t - 128 < M) {
-            double a0 = 0.0, a1 = 0.0, v1 = 0.0;
-#pragma unroll
-            for (int j = 0; j < KB; ++j) {
-                if (j < K) {
-                    if (j & 1) a1 = fma(x[j], zv[j], a1);
-                    else a0 = fma(x[j], zv[j], a0);
-                } else if (j == K) {
-                    v1 = x[j];
-                }
+        // pivot rows: v1_j + (X z)_j from the rows of [X v1]
+        if (t < M) {
+            const double *xr = Xs + t * ldx;
+            double a0 = 0.0, a1 = 0.0;
+            int j = 0;
+            for (; j + 1 < K; j += 2) {
+                a0 = fma(xr[j], zv[j], a0);
+                a1 = fma(xr[j + 1], zv[j + 1], a1);
             }
-            w[ipiv[t - 128]] = (v1 + (a0 + a1)) / s2;
+            if (j < K) a0 = fma(xr[j], zv[j], a0);
+            w[ipiv[t]] = (xr[K] + (a0 + a1)) / s2;
         }
     }
     __syncthreads();
