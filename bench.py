@@ -376,12 +376,14 @@ def run_cube8m(mode_name, target, piece_steps=40000, max_steps=3_000_000, cpu_sw
 
 
 def ns_flops(n, M):
-    """FP64 flops the null-space weight solver executes for one system of n
+    """FP64 flops of the null-space weight solver's steps for one system of n
     support nodes and M monomials (K = n - M): the LU of P with the extra
     right-hand-side row, the K + 1 triangular solves for [X v1], the block
     products T = A [G v] (pivot columns only) and C_aug = [G v]^T T (lower
     triangle), the Cholesky of C with the reduced right-hand side as an
-    extra row, the backward substitution and w = v + G z."""
+    extra row, the backward substitution and w = v + G z.  Work the kernels
+    also do on tile padding and on the upper halves of diagonal tiles is not
+    counted."""
     K = n - M
     lu = sum(2 * (n - k) * (M - k - 1) for k in range(M))
     xs = (K + 1) * M * (M - 1)
