@@ -277,7 +277,7 @@ template <int DIM, int MB, int KB>
 __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, double *lds) {
     const int t = threadIdx.x;
     const int lane = t & 63;
-    const int wave = t >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: scalar branches on it
     const int64_t li = it.first;
     const int64_t c = cx.rows[li];
     const int n = cx.nrow[c];
@@ -593,8 +593,14 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
     const double tinyC = group_max(dmax, t, kLT, red) * 0x1p-45;
     // in-wavefront factorization of column block cb (diagonal tile T[0]);
     // L's row K multipliers go to yv, 1 / L[k][k] to ldiag
+    // Step k subtracts C[i][k] C[k][j] / d from every element of the block's
+    // columns j > k (lanes of other columns take a zero factor; the upper
+    // half of the diagonal tile is updated too, and never read again), and
+    // the division of column k by sqrt(d) waits to the block's end: no later
+    // step of the block reads column k.
     auto factor = [&](auto &T, int cb) __attribute__((always_inline)) {
         constexpr int NT = sizeof(T) / sizeof(T[0]);
+        double myrd = 1.0;  // 1 / d of this lane's column
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const int gk = 16 * cb + k;
@@ -603,21 +609,16 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
                 if (!(d > tinyC)) {
                     bad = true;  // uniform in the wavefront
                 } else {
-                    const double rd = 1.0 / d, rl = sqrt(rd);
-                    const double cjr = lane_perm(T[0][k / 4], (k % 4) * 16 + l16) * rd;  // C[k][j] / d
+                    const double rd = 1.0 / d;
+                    const double cj = lane_perm(T[0][k / 4], (k % 4) * 16 + l16);  // C[k][j]
+                    const double cjr = l16 > k ? cj * rd : 0.0;
+                    myrd = l16 == k ? rd : myrd;
 #pragma unroll
                     for (int dd = 0; dd < NT; ++dd)
                         if (cb + dd < nJ) {
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                const int i = lq + 4 * r;
-                                const double ci = row_bcast(T[dd][r], k);  // C[i][k]
-                                const double v = fma(-ci, cjr, T[dd][r]);
-                                T[dd][r] = (l16 > k && (dd > 0 || i > k)) ? v : T[dd][r];
-                                T[dd][r] = (l16 == k && (dd > 0 || i >= k)) ? T[dd][r] * rl : T[dd][r];
-                            }
+                            for (int r = 0; r < 4; ++r) T[dd][r] = fma(-row_bcast(T[dd][r], k), cjr, T[dd][r]);
                         }
-                    if (lane == 0) ldiag[gk] = rl;
                 }
             }
         }
@@ -625,11 +626,14 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
             if (lane == 0) *cflag = 1;
             return;
         }
+        const double myrl = sqrt(myrd);  // 1 / L[j][j]
+        if (lq == 0 && 16 * cb + l16 < K) ldiag[16 * cb + l16] = myrl;
 #pragma unroll
         for (int dd = 0; dd < NT; ++dd)
             if (cb + dd < nJ) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
+                    T[dd][r] *= myrl;
                     const int gi = 16 * (cb + dd) + lq + 4 * r, gj = 16 * cb + l16;
                     if (gi == K && gj < K) yv[gj] = T[dd][r];
                     if (dd > 0) stg[(dd * 16 + l16) * 16 + lq + 4 * r] = T[dd][r];
