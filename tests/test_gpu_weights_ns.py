@@ -32,8 +32,12 @@ def _weights(xyz, typ, n, m, normals=None):
     return out
 
 
+# K = n - M: 35, 84, 28, 30, 15 (one 16-column block), and 16, 32, 80 (a
+# multiple of 16: the reduced right-hand side row K alone in the last block,
+# which has no pivot column)
 @pytest.mark.parametrize("dim,side,m,n,seed", [(3, 12, 4, 70, 71), (3, 11, 6, 168, 72), (2, 24, 6, 56, 73),
-                                               (3, 10, 3, 50, 74), (2, 30, 4, 30, 75)])
+                                               (3, 10, 3, 50, 74), (2, 30, 4, 30, 75), (3, 9, 4, 51, 78),
+                                               (3, 9, 4, 67, 79), (3, 11, 6, 164, 80)])
 def test_ns_weights_match_oracle(dim, side, m, n, seed):
     print(f"null-space weights: dim={dim} side={side} m={m} n={n}", flush=True)
     xyz, typ = ri.jittered_grid(dim, side, 0.3, seed)
