@@ -111,6 +111,24 @@ def time_sweeps(s, steps, warmup, chunk=500):
     return t1 - t0, per_sweep, nsw, rep, warm
 
 
+def sweep_windows(s, windows=5, steps=1000, chunk=500):
+    """Device time per sweep over `windows` further windows of `steps` steps
+    (HIP events around the chunk graphs, which the timed call has already
+    built): median, minimum and maximum, in ms per sweep."""
+    import numpy as np
+    import torch
+    p, wl = s["p"], s["wl"]
+    per = []
+    for _ in range(windows):
+        u = s["u0"].clone()
+        st, _ = p.iterate(s["f"], u, wl.dt, steps, 0.0, chunk)
+        assert st == 0, st
+        per.append(1e3 * p.last_sweep_time()[0])
+    torch.cuda.synchronize()
+    return {"windows": windows, "steps_each": steps, "median_ms_per_sweep": round(float(np.median(per)), 5),
+            "min_ms_per_sweep": round(min(per), 5), "max_ms_per_sweep": round(max(per), 5)}
+
+
 def time_to_error(s, target, inner=500, max_steps=2_000_000):
     """Steps and device time until max|u - u_exact| <= target, plain FP64 vs
     FP32 inner sweeps with FP64 outer correction (checked every `inner` steps
@@ -1007,6 +1025,8 @@ def main():
                  "sweep_shape": {k[4:]: v for k, v in info.items() if k.startswith("f64_")},
                  "coded_slices_frac": round(info["coded_slices"] / max(1, info["slices"]), 4),
                  "setup": {k: round(v, 3) for k, v in s["setup"].items()}}
+        if i == 0:
+            entry["event_windows"] = sweep_windows(s)
         per_order[m] = entry
         if i == 0:
             head = (s, entry, wall, per_sweep, nsw)
