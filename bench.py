@@ -1041,7 +1041,9 @@ def main():
     alg_bytes = entry["alg_bytes_per_update"] * entry["interior_nodes"]
     roofline = {"bound": "hbm", "achieved": round(alg_bytes / per_sweep / 1e9, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(alg_bytes / per_sweep / 1e9 / PEAK_HBM_GBS, 4),
-                "traffic": traffic, "kernel": "k_sweep_f64", "alg_bytes_per_launch": alg_bytes,
+                "traffic": traffic,
+                "traffic_GBps": round(traffic / per_sweep / 1e9, 1) if traffic else None,
+                "kernel": "k_sweep_f64", "alg_bytes_per_launch": alg_bytes,
                 "avg_launch_ms": round(1e3 * per_sweep, 5), "launches_timed": nsw,
                 "format_bytes_per_launch": entry["format_bytes_per_sweep"],
                 "format_frac": round(entry["format_GBps"] / PEAK_HBM_GBS, 4), "sweep_shape": entry["sweep_shape"]}
