@@ -24,7 +24,11 @@
 //      extra row that is eliminated but never chosen as pivot: its
 //      multipliers are U^{-T} Lp.  Per column one barrier: each wavefront
 //      posts its best candidate row (largest |entry|, lowest row on ties) to
-//      LDS, every lane takes the winner and eliminates;
+//      LDS, every lane takes the winner and eliminates within the column's
+//      panel of kPW columns; at a panel's end the columns past it take the
+//      panel's kPW updates at once (U12 = L11^{-1} A12 by one lane per
+//      column, then every free row subtracts l_k U12[k] in pivot order: the
+//      products and their order of the column-by-column elimination);
 //   3. every non-pivot row (and the extra row) solves L1^T xi = its
 //      multipliers with the rows of L1 from LDS: -xi is its column of X
 //      (the extra row's xi is v1); [X v1] goes to LDS;
@@ -52,6 +56,7 @@ namespace rbf {
 namespace {
 
 constexpr int kLT = 256;        // threads per workgroup
+constexpr int kPW = 8;          // LU panel width (columns updated per pivot step)
 constexpr int kLW = kLT / 64;   // wavefronts
 
 // v_mfma_f64_16x16x4f64 (D = A B + C; A 16x4, B 4x16): lane l holds
@@ -94,6 +99,7 @@ __host__ __device__ inline LuLayout lu_layout(int n, int M, int MB, int KB) {
     o += 64;
     L.xreg = o;                // LU candidate rows, then L1, then [X v1]
     int xr = 8 * kLW + 2 * kLW * MB;
+    if (MB > kPW) xr += kPW * kPW + kPW * (MB - kPW + 2);  // a panel's L11 and U12 (LU in kPW-column panels)
     if (l1_off(M) + 2 > xr) xr = l1_off(M) + 2;
     if (M * L.ldx > xr) xr = M * L.ldx;
     o += xr + (xr & 1);
@@ -362,7 +368,7 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
             volatile lds_f64 *sl = (volatile lds_f64 *)(slots + opaque(((k1 & 1) * kLW + wave) * MB));
 #pragma unroll
             for (int j = 0; j < MB; ++j)
-                if (j > k1) sl[j] = x[j];
+                if (j > k1 && j < (k1 / kPW) * kPW + kPW) sl[j] = x[j];  // the rest of its panel
 #pragma unroll
             for (int j = 0; j < MB; ++j)
                 if (j == k1) h[3] = 1.0 / x[j];
@@ -394,14 +400,53 @@ __device__ __forceinline__ void solve_lu_item(const WCtx &cx, const Item &it, do
                     isfree = false;
                     mystep = k;
                 }
+                const int pe = (k / kPW) * kPW + kPW < MB ? (k / kPW) * kPW + kPW : MB;  // end of k's panel
                 if (isfree || row == n) {
                     const double l = x[k] * rpv;
                     x[k] = l;
-                    row_axpy<MB, 4>(x, u, l, k + 1, MB);
+                    row_axpy<MB, 4>(x, u, l, k + 1, pe);
                 }
-                if (k + 1 < M) post(k + 1, isfree ? fabs(x[k + 1]) : -1.0);
+                if (k + 1 < M && k + 1 < pe) post(k + 1, isfree ? fabs(x[k + 1]) : -1.0);
                 __syncthreads();
             }
+        }
+        if (k % kPW == kPW - 1 && k + 1 < MB && k + 1 < M && !bad) {
+            // end of panel p: the columns past it get the panel's kPW updates
+            // at once.  The panel's pivot rows post their entries there (A12)
+            // and their multipliers of the panel's earlier pivots (L11); one
+            // lane per column takes U12 = L11^{-1} A12 in pivot order (the
+            // values those rows had when chosen); every free row then
+            // subtracts l_k U12[k] for k in pivot order: per element the
+            // products and their order of the column-by-column elimination.
+            const int p = k / kPW, c0 = kPW * (p + 1), TP = (MB - c0 + 1) & ~1;
+            double *L11 = slots + 2 * kLW * MB, *U12 = L11 + kPW * kPW;
+            if (mystep >= kPW * p && mystep < c0) {
+                const int kk = mystep - kPW * p;
+#pragma unroll
+                for (int j = 0; j < kPW; ++j)
+                    if (j < kk) L11[kk * kPW + j] = x[kPW * p + j];
+#pragma unroll
+                for (int j = c0; j < MB; ++j) U12[kk * TP + (j - c0)] = x[j];
+            }
+            __syncthreads();
+            for (int j = t; j < TP; j += kLT) {
+                double uu[kPW];
+#pragma unroll
+                for (int q = 0; q < kPW; ++q) uu[q] = U12[q * TP + j];
+#pragma unroll
+                for (int q = 1; q < kPW; ++q)
+#pragma unroll
+                    for (int r = 0; r < q; ++r) uu[q] = fma(-L11[q * kPW + r], uu[r], uu[q]);
+#pragma unroll
+                for (int q = 0; q < kPW; ++q) U12[q * TP + j] = uu[q];
+            }
+            __syncthreads();
+            if (isfree || row == n) {
+#pragma unroll
+                for (int q = 0; q < kPW; ++q) row_axpy<MB, 4>(x, U12 + q * TP - c0, x[kPW * p + q], c0, MB);
+            }
+            post(c0, isfree ? fabs(x[c0]) : -1.0);
+            __syncthreads();
         }
     }
 
