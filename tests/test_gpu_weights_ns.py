@@ -34,10 +34,12 @@ def _weights(xyz, typ, n, m, normals=None):
 
 # K = n - M: 35, 84, 28, 30, 15 (one 16-column block), and 16, 32, 80 (a
 # multiple of 16: the reduced right-hand side row K alone in the last block,
-# which has no pivot column)
+# which has no pivot column); the last three reach the compiled sizes
+# (3D, 56, 64), (2D, 64, 64) and (2D, 24, 24)
 @pytest.mark.parametrize("dim,side,m,n,seed", [(3, 12, 4, 70, 71), (3, 11, 6, 168, 72), (2, 24, 6, 56, 73),
                                                (3, 10, 3, 50, 74), (2, 30, 4, 30, 75), (3, 9, 4, 51, 78),
-                                               (3, 9, 4, 67, 79), (3, 11, 6, 164, 80)])
+                                               (3, 9, 4, 67, 79), (3, 11, 6, 164, 80), (3, 10, 5, 112, 81),
+                                               (2, 30, 6, 80, 82), (2, 24, 5, 40, 83)])
 def test_ns_weights_match_oracle(dim, side, m, n, seed):
     print(f"null-space weights: dim={dim} side={side} m={m} n={n}", flush=True)
     xyz, typ = ri.jittered_grid(dim, side, 0.3, seed)
