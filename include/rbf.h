@@ -140,7 +140,8 @@ rbf_status rbf_build_stencils(rbf_handle *h, int32_t n_uniform, const int16_t *n
  * keep_fp32: also keep an FP32 copy (needed by the mixed-precision mode).
  * Solvers:
  * - systems of more than 40 unknowns with m >= 1, 2 or 3 dimensions,
- *   n <= 255 and M, n - M + 1 <= 88 (3D) or 64 (2D): a null-space method.
+ *   n <= 255, M <= 84 and n - M + 1 <= 86 (3D) or M, n - M + 1 <= 64 (2D):
+ *   a null-space method.
  *   P = [L1; L2] U by LU with partial pivoting (rows reordered pivots
  *   first), w = v + G z with G = [-L1^{-T} L2^T; I] spanning the null space
  *   of P^T and P^T v = Lp, and (G^T A G) z = G^T (L Phi - A v) by Cholesky
